@@ -1,0 +1,141 @@
+/*
+ * fock.h - C ABI of the MI355X screened exact-exchange library (libfock.so).
+ *
+ * The library applies the exact-exchange (Fock) operator of plane-wave
+ * hybrid-functional DFT and evaluates the exchange energy and its gradient:
+ *
+ *   (V_x u)_{k,n} = - sum_{k',m} w_{k'} f_{k',m} u_{k',m} * IDFT[ v_q * DFT( conj(u_{k',m}) u_{k,n} ) ]
+ *   E_x           = -1/2 sum_{k,n,k',m} w_k f_{k,n} w_{k'} f_{k',m} (Omega/N^2) sum_c v_q(c) |DFT(conj(u_{k',m}) u_{k,n})(c)|^2
+ *
+ * which is the paper's Eq. (2) (section "Our Implementation": four nested
+ * loops, k-points outer, band pairs inner) written on the FFT grid, with the
+ * screened kernel of HSE06 (paper, Introduction):
+ *
+ *   v_q(c) = 4 pi/|K|^2 (1 - exp(-|K|^2/(4 mu^2))),  K = sum_i (g_i(c) + q_i) b_i,  v(K=0) = pi/mu^2,
+ *   q = k - k' (fractional, never folded), g_i(c) the integer representative of
+ *   class c_i in (-N_i/2, N_i/2); for even N_i the Nyquist class c_i = N_i/2 takes
+ *   the mean of v over both representatives +-N_i/2 (and over all 2^d
+ *   combinations when d axes sit at Nyquist).
+ *
+ * Conventions
+ *   lattice   rows a1, a2, a3 in bohr (Cartesian); Omega = |det|; b_i = 2 pi (A^-T) rows.
+ *   grid      N1, N2, N3; orbital element j = (j1*N2 + j2)*N3 + j3 is the value at
+ *             r = sum_i (j_i/N_i) a_i of the PERIODIC PART u of the Bloch orbital.
+ *   DFT       forward unnormalised with exp(-2 pi i c.j/N); inverse carries 1/N.
+ *   psi       per instance, complex (interleaved re, im), [nk][nbands][band_stride];
+ *             element (k, n, j) at psi[(k*nbands + n)*band_stride + j].
+ *   occ       per instance, device FP64 [nk][nbands] (f_{k,n}; fractional allowed).
+ *   weights   w_k from the descriptor (host), default 1/nk.
+ *
+ * Precision: FOCK_C128 computes in complex128 throughout.  FOCK_C64 takes
+ * complex64 orbitals and runs co-densities, FFTs, the kernel multiply and the
+ * accumulate in FP32; the kernel table and the twiddles are built in FP64 and
+ * rounded once, and per-pair energies are accumulated in FP64.
+ *
+ * Errors: every function returns a fock_status and never aborts.  Argument
+ * errors are detected before any device work and leave outputs untouched.
+ * fock_last_error() returns a thread-local description of the last non-OK
+ * status.  Asynchronous device faults surface at the caller's next
+ * synchronisation.
+ *
+ * Concurrency: all device work is enqueued on the plan's stream with no host
+ * synchronisation.  A plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef FOCK_H
+#define FOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fock_plan_s* fock_plan_t; /* opaque, owned by the library */
+
+typedef enum {
+  FOCK_OK = 0,
+  FOCK_ERR_ARG = 1,         /* invalid argument (NULL, out of range, non-finite, singular cell) */
+  FOCK_ERR_UNSUPPORTED = 2, /* valid but not supported (grid axis not {2,3,5}-smooth or > 72)     */
+  FOCK_ERR_NOMEM = 3,       /* host allocation failed, or workspace smaller than required          */
+  FOCK_ERR_DEVICE = 4,      /* no usable GPU, or a HIP call / kernel launch failed                */
+  FOCK_ERR_STATE = 5        /* call out of order (e.g. apply before fock_set_workspace)           */
+} fock_status;
+
+typedef enum { FOCK_C128 = 0, FOCK_C64 = 1 } fock_precision;
+
+/* One exchange problem ("instance").  All pointers are HOST pointers and are
+ * only read during fock_plan. */
+typedef struct {
+  double lattice[9];       /* rows a1, a2, a3, bohr                                          */
+  int32_t grid[3];         /* N1, N2, N3: each in [2, 72] with prime factors in {2, 3, 5}    */
+  int32_t nk;              /* k-points of the orbital set, >= 1                              */
+  const double* kfrac;     /* [nk][3] fractional (reciprocal-basis) coordinates              */
+  const double* kweight;   /* [nk] finite, >= 0; NULL means 1/nk                             */
+  int32_t npairs;          /* 0: every k' for every k; else the number of (k, k') below      */
+  const int32_t* kpairs;   /* [npairs][2] (ik, ik'): the k' summed for output k              */
+  int32_t nbands;          /* bands per k, >= 1                                              */
+  int64_t band_stride;     /* elements between consecutive bands, >= N1*N2*N3                */
+  double mu;               /* screening parameter in bohr^-1, finite and > 0                 */
+} fock_desc;
+
+/* Build a plan for n_inst independent instances of one precision (paper,
+ * "Our Implementation": the band loops of every k-point pair go to the GPU).
+ * Host work only: validates the descriptors, builds the FP64 kernel tables
+ * v_q for every distinct transfer q, the twiddle tables, and the batched
+ * schedule of band pairs.  `hip_stream` is a hipStream_t (NULL: default
+ * stream).  On success *out owns host memory only; release with fock_destroy. */
+fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
+                      fock_plan_t* out);
+
+/* Bytes of device workspace the plan needs (tables, schedule, scratch). */
+fock_status fock_workspace_size(fock_plan_t plan, size_t* bytes);
+
+/* Attach caller-owned device memory of at least fock_workspace_size bytes
+ * (256-byte aligned) and upload the tables on the plan stream.  The memory
+ * must stay valid until fock_destroy or the next fock_set_workspace.
+ * Returns FOCK_ERR_DEVICE when no GPU is usable. */
+fock_status fock_set_workspace(fock_plan_t plan, void* dev_ptr, size_t bytes);
+
+/* Change the stream later calls enqueue on. */
+fock_status fock_set_stream(fock_plan_t plan, void* hip_stream);
+
+/* V_x u for every (k, n) of every instance (the paper's FOCK_ACC,
+ * "CPU Performance Analysis").  psi[i], vx_psi[i]: device pointers in the psi
+ * layout of instance i (vx_psi may not alias psi); occ[i]: device FP64
+ * [nk][nbands].  vmat: NULL, or per instance a device pointer to the band
+ * overlap M[k][i][j] = Omega/N sum_j conj(u_{k,i}) (V_x u)_{k,j} in the
+ * instance's complex precision, layout [nk][nbands][nbands].  The pointer
+ * arrays themselves are host arrays of length n_inst. */
+fock_status fock_apply(fock_plan_t plan, const void* const* psi, const double* const* occ, void* const* vx_psi,
+                       void* const* vmat);
+
+/* E_x of every instance (paper Eq. (2), negative sign: exchange lowers the
+ * energy) into device FP64 ex[n_inst].  Per-pair sums are FP64 and reduced in
+ * a fixed order, so FP64 results are bitwise reproducible. */
+fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* const* occ, double* ex);
+
+/* Gradient of E_x: grad_psi[i] (psi layout, device) receives
+ *   grad_ex[i] * scale * w_k * f_{k,n} * (V_x u)_{k,n}
+ * with grad_ex a device FP64 array [n_inst] and scale a host number; the
+ * co-densities are recomputed, never stored.  dE_x/d conj(u_{k,n}) is
+ * scale = Omega/N; torch's complex-gradient convention is scale = 2 Omega/N. */
+fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const double* const* occ,
+                                 const double* grad_ex, double scale, void* const* grad_psi);
+
+/* Counters of the plan: ordered band pairs per apply (N_k^2 N_b^2 summed over
+ * instances, or per the k-pair lists), band-pair FFT round trips per apply,
+ * FFT pairs per energy evaluation, and kernel launches per apply. */
+fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* apply_fft_pairs,
+                            int64_t* energy_fft_pairs, int64_t* apply_launches);
+
+/* Release the plan (host memory; the caller frees the workspace). NULL is a no-op. */
+fock_status fock_destroy(fock_plan_t plan);
+
+const char* fock_status_string(fock_status s);
+const char* fock_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOCK_H */

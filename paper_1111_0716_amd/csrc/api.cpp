@@ -1,0 +1,245 @@
+// C ABI of libfock.so (declared in include/fock.h).
+#include <cmath>
+#include <cstdint>
+#include <new>
+#include <string>
+
+#include "fock_internal.hpp"
+
+namespace fock {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+fock_status set_error(fock_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+fock_status validate_desc(const fock_desc& d, int idx);
+fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, Plan** out);
+hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
+
+namespace {
+
+fock_status device_ok() {
+  int n = 0;
+  const hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return set_error(FOCK_ERR_DEVICE, "no usable GPU (hipGetDeviceCount)");
+  }
+  return FOCK_OK;
+}
+
+fock_status check_ready(const Plan* p) {
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  if (!p->uploaded || !p->ws) return set_error(FOCK_ERR_STATE, "no workspace attached (call fock_set_workspace)");
+  return FOCK_OK;
+}
+
+fock_status check_ptrs(const Plan* p, const void* const* a, const char* what) {
+  if (!a) return set_error(FOCK_ERR_ARG, std::string(what) + " array is NULL");
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (!a[i]) return set_error(FOCK_ERR_ARG, std::string(what) + "[" + std::to_string(i) + "] is NULL");
+  return FOCK_OK;
+}
+
+fock_status hip_fail(hipError_t e, const char* where) {
+  (void)hipGetLastError();  // do not leave a sticky error for the caller's next HIP call
+  return set_error(FOCK_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool has_empty_k(const Instance& in) {
+  for (const auto& v : in.kpartners)
+    if (v.empty()) return true;
+  return false;
+}
+
+// apply and backward share the batch loop; they differ in the output factor
+fock_status run_apply(Plan* p, const void* const* psi, const double* const* occ, void* const* out,
+                      const double* gscale, double hscale, bool backward) {
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    if (has_empty_k(p->inst[i])) {
+      const hipError_t e = launch_zero_outputs(*p, static_cast<int>(i), out[i]);
+      if (e != hipSuccess) return hip_fail(e, "zero outputs");
+    }
+  }
+  for (const Batch& b : p->apply_batches) {
+    const hipError_t e = launch_apply_batch(*p, b, psi[b.inst], occ[b.inst], out[b.inst],
+                                            gscale ? gscale + b.inst : nullptr, hscale, backward);
+    if (e != hipSuccess) return hip_fail(e, "apply batch launch");
+  }
+  return FOCK_OK;
+}
+
+}  // namespace
+}  // namespace fock
+
+using namespace fock;
+
+extern "C" {
+
+fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
+                      fock_plan_t* out) {
+  clear_error();
+  if (!out) return set_error(FOCK_ERR_ARG, "out is NULL");
+  if (!descs) return set_error(FOCK_ERR_ARG, "descs is NULL");
+  if (n_inst < 1) return set_error(FOCK_ERR_ARG, "n_inst < 1");
+  if (prec != FOCK_C128 && prec != FOCK_C64) return set_error(FOCK_ERR_ARG, "unknown precision");
+  for (int i = 0; i < n_inst; ++i) {
+    const fock_status s = validate_desc(descs[i], i);
+    if (s != FOCK_OK) return s;
+  }
+  try {
+    Plan* p = nullptr;
+    const fock_status s = build_plan(descs, n_inst, prec, hip_stream, &p);
+    if (s != FOCK_OK) return s;
+    *out = reinterpret_cast<fock_plan_t>(p);
+    return FOCK_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(FOCK_ERR_NOMEM, "host allocation failed while planning");
+  } catch (...) {
+    return set_error(FOCK_ERR_ARG, "planning failed");
+  }
+}
+
+fock_status fock_workspace_size(fock_plan_t plan, size_t* bytes) {
+  clear_error();
+  if (!plan || !bytes) return set_error(FOCK_ERR_ARG, "NULL argument");
+  *bytes = reinterpret_cast<Plan*>(plan)->total_bytes;
+  return FOCK_OK;
+}
+
+fock_status fock_set_workspace(fock_plan_t plan, void* dev_ptr, size_t bytes) {
+  clear_error();
+  if (!plan || !dev_ptr) return set_error(FOCK_ERR_ARG, "NULL argument");
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % 256 != 0) return set_error(FOCK_ERR_ARG, "workspace not 256-byte aligned");
+  if (bytes < p->total_bytes)
+    return set_error(FOCK_ERR_NOMEM, "workspace of " + std::to_string(bytes) + " bytes < required " +
+                                         std::to_string(p->total_bytes));
+  fock_status s = device_ok();
+  if (s != FOCK_OK) return s;
+  hipError_t e = prepare_kernels(p->prec, &p->max_lds);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return hip_fail(e, "device query");
+  }
+  if (p->lds_needed > p->max_lds)
+    return set_error(FOCK_ERR_UNSUPPORTED, "grid needs " + std::to_string(p->lds_needed) +
+                                               " bytes of LDS per workgroup; the device allows " +
+                                               std::to_string(p->max_lds));
+  p->ws = static_cast<unsigned char*>(dev_ptr);
+  p->ws_bytes = bytes;
+  e = hipMemcpyAsync(p->ws, p->host_image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    p->ws = nullptr;
+    return hip_fail(e, "table upload");
+  }
+  p->uploaded = true;
+  return FOCK_OK;
+}
+
+fock_status fock_set_stream(fock_plan_t plan, void* hip_stream) {
+  clear_error();
+  if (!plan) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  reinterpret_cast<Plan*>(plan)->stream = static_cast<hipStream_t>(hip_stream);
+  return FOCK_OK;
+}
+
+fock_status fock_apply(fock_plan_t plan, const void* const* psi, const double* const* occ, void* const* vx_psi,
+                       void* const* vmat) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
+  s = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false);
+  if (s != FOCK_OK) return s;
+  if (vmat) {
+    for (size_t i = 0; i < p->inst.size(); ++i) {
+      if (!vmat[i]) continue;
+      const hipError_t e = launch_overlap(*p, static_cast<int>(i), psi[i], vx_psi[i], vmat[i]);
+      if (e != hipSuccess) return hip_fail(e, "overlap launch");
+    }
+  }
+  return FOCK_OK;
+}
+
+fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* const* occ, double* ex) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+  if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
+  for (const Batch& b : p->energy_batches) {
+    const hipError_t e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
+    if (e != hipSuccess) return hip_fail(e, "energy batch launch");
+  }
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    const hipError_t e = launch_energy_finish(*p, static_cast<int>(i), ex + i);
+    if (e != hipSuccess) return hip_fail(e, "energy finish launch");
+  }
+  return FOCK_OK;
+}
+
+fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const double* const* occ,
+                                 const double* grad_ex, double scale, void* const* grad_psi) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(grad_psi), "grad_psi")) != FOCK_OK) return s;
+  if (!grad_ex) return set_error(FOCK_ERR_ARG, "grad_ex is NULL");
+  if (!std::isfinite(scale)) return set_error(FOCK_ERR_ARG, "scale not finite");
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (grad_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "grad_psi aliases psi");
+  return run_apply(p, psi, occ, grad_psi, grad_ex, scale, true);
+}
+
+fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* apply_fft_pairs,
+                            int64_t* energy_fft_pairs, int64_t* apply_launches) {
+  clear_error();
+  if (!plan) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  const Plan* p = reinterpret_cast<const Plan*>(plan);
+  if (ordered_pairs) *ordered_pairs = p->ordered_pairs;
+  if (apply_fft_pairs) *apply_fft_pairs = p->apply_fft_pairs;
+  if (energy_fft_pairs) *energy_fft_pairs = p->energy_fft_pairs;
+  if (apply_launches) *apply_launches = p->apply_launches;
+  return FOCK_OK;
+}
+
+fock_status fock_destroy(fock_plan_t plan) {
+  clear_error();
+  delete reinterpret_cast<Plan*>(plan);
+  return FOCK_OK;
+}
+
+const char* fock_status_string(fock_status s) {
+  switch (s) {
+    case FOCK_OK: return "FOCK_OK";
+    case FOCK_ERR_ARG: return "FOCK_ERR_ARG: invalid argument";
+    case FOCK_ERR_UNSUPPORTED: return "FOCK_ERR_UNSUPPORTED: unsupported size or option";
+    case FOCK_ERR_NOMEM: return "FOCK_ERR_NOMEM: out of memory or workspace too small";
+    case FOCK_ERR_DEVICE: return "FOCK_ERR_DEVICE: GPU unavailable or HIP error";
+    case FOCK_ERR_STATE: return "FOCK_ERR_STATE: call out of order";
+  }
+  return "unknown fock_status";
+}
+
+const char* fock_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

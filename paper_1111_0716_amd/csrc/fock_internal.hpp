@@ -1,0 +1,93 @@
+// Internal plan representation shared by the host planner, the C ABI and
+// the kernel launchers of libfock.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fock.h"
+
+namespace fock {
+
+// One ordered pair of an energy batch: output (k, n), partner (k', m), table
+// q and multiplicity (2 when the swapped pair is folded in, else 1).
+struct PairRef {
+  int32_t k, n, kp, m, q, mult;
+};
+
+// A batch of band pairs.
+//   apply:  outputs o0..o0+nO-1 (global band index k*nbands + n, all with the
+//           same partner list) times partners (k', m) stored as int2 at
+//           part_off; every output block is covered by consecutive batches,
+//           the first of which writes its outputs (the rest add).
+//   energy: an explicit PairRef list at pair_off; its partial sum goes to slot.
+struct Batch {
+  int32_t inst = 0;
+  int32_t o0 = 0, nO = 0;
+  size_t part_off = 0;  // bytes into the workspace
+  int32_t nP = 0;
+  int32_t first = 0;
+  size_t pair_off = 0;  // bytes into the workspace
+  int32_t npairs = 0;   // pairs in the batch (apply: nO*nP)
+  int32_t slot = 0;
+};
+
+struct Instance {
+  double lattice[9];
+  int grid[3];
+  int nk;
+  std::vector<double> kfrac, kweight;
+  std::vector<std::vector<int>> kpartners;  // k -> list of k'
+  bool symmetric = true;                     // (k, k') listed iff (k', k) listed
+  int nbands;
+  int64_t band_stride;
+  double mu;
+  int64_t npts;
+  double omega;
+  int nq = 0;
+  std::vector<int> qmap;  // [nk*nk] -> table index or -1
+  // workspace offsets (bytes)
+  size_t vtab_off = 0, kw_off = 0, qmap_off = 0;
+  int first_ebatch = 0, n_ebatches = 0;
+};
+
+struct Plan {
+  fock_precision prec;
+  size_t csize;  // sizeof(complex element)
+  hipStream_t stream = nullptr;
+  std::vector<Instance> inst;
+  std::vector<Batch> apply_batches, energy_batches;
+  // workspace layout (bytes)
+  size_t tw_off = 0;                  // twiddle tables
+  size_t const_bytes = 0;             // uploaded prefix
+  size_t tbuf_off = 0, tbuf_bytes = 0;
+  size_t epart_off = 0, epart_bytes = 0;
+  size_t ebsum_off = 0, ebsum_bytes = 0;
+  size_t total_bytes = 0;
+  std::vector<unsigned char> host_image;  // constant prefix, uploaded by set_workspace
+  unsigned char* ws = nullptr;            // device workspace (caller-owned)
+  size_t ws_bytes = 0;
+  bool uploaded = false;
+  int64_t ordered_pairs = 0, apply_fft_pairs = 0, energy_fft_pairs = 0, apply_launches = 0;
+  int max_pairs_per_batch = 0;
+  size_t max_lds = 0;      // per-block LDS limit of the device
+  size_t lds_needed = 0;   // largest dynamic LDS of any launch (+ static)
+};
+
+// status helpers (thread-local last error)
+fock_status set_error(fock_status s, const std::string& msg);
+void clear_error();
+
+// kernel launchers (kernels.hip); return hipSuccess or the launch error
+hipError_t prepare_kernels(fock_precision prec, size_t* max_lds);
+hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* vx,
+                              const double* gscale, double hscale, bool backward);
+hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
+hipError_t launch_energy_finish(const Plan& p, int inst, double* ex);
+hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
+hipError_t launch_overlap(const Plan& p, int inst, const void* psi, const void* vx, void* vmat);
+
+}  // namespace fock

@@ -1,0 +1,388 @@
+// Host planner of libfock.so: descriptor validation, FP64 kernel tables,
+// twiddle tables, the batched band-pair schedule and the workspace layout.
+// Host work only; nothing here touches the device.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <memory>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fft_lds.hpp"
+#include "fock_internal.hpp"
+
+namespace fock {
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_all(const double* p, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+double det3(const double* a) {
+  return a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) + a[2] * (a[3] * a[7] - a[4] * a[6]);
+}
+
+// b_i rows with a_i . b_j = 2 pi delta_ij, i.e. B = 2 pi A^{-T}
+void reciprocal(const double* a, double b[3][3]) {
+  const double d = det3(a);
+  const double two_pi = 6.283185307179586476925286766559;
+  // inverse of A (rows a_i), then transpose
+  double inv[3][3];
+  inv[0][0] = (a[4] * a[8] - a[5] * a[7]) / d;
+  inv[0][1] = (a[2] * a[7] - a[1] * a[8]) / d;
+  inv[0][2] = (a[1] * a[5] - a[2] * a[4]) / d;
+  inv[1][0] = (a[5] * a[6] - a[3] * a[8]) / d;
+  inv[1][1] = (a[0] * a[8] - a[2] * a[6]) / d;
+  inv[1][2] = (a[2] * a[3] - a[0] * a[5]) / d;
+  inv[2][0] = (a[3] * a[7] - a[4] * a[6]) / d;
+  inv[2][1] = (a[1] * a[6] - a[0] * a[7]) / d;
+  inv[2][2] = (a[0] * a[4] - a[1] * a[3]) / d;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) b[i][j] = two_pi * inv[j][i];
+}
+
+// Screened kernel of HSE06: 4 pi/K^2 (1 - exp(-K^2/(4 mu^2))), K -> 0 limit pi/mu^2.
+inline double screened(double k2, double mu) {
+  if (k2 == 0.0) return M_PI / (mu * mu);
+  return -4.0 * M_PI / k2 * std::expm1(-k2 / (4.0 * mu * mu));
+}
+
+// v_q on every class of the grid divided by N, Nyquist classes averaged over
+// their +-N/2 aliases (all combinations when several axes sit at Nyquist).
+void build_kernel_table(const Instance& in, const double q[3], std::vector<double>& out) {
+  double b[3][3];
+  reciprocal(in.lattice, b);
+  // per axis and class: the Cartesian vectors (g + q_i) b_i of its representatives
+  std::vector<std::vector<std::array<double, 3>>> reps[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    const int n = in.grid[ax];
+    reps[ax].resize(n);
+    for (int c = 0; c < n; ++c) {
+      std::vector<double> gs;
+      if (2 * c == n) {
+        gs = {static_cast<double>(c), static_cast<double>(c - n)};
+      } else if (2 * c < n) {
+        gs = {static_cast<double>(c)};
+      } else {
+        gs = {static_cast<double>(c - n)};
+      }
+      for (double g : gs) {
+        const double x = g + q[ax];
+        reps[ax][c].push_back({x * b[ax][0], x * b[ax][1], x * b[ax][2]});
+      }
+    }
+  }
+  const int n1 = in.grid[0], n2 = in.grid[1], n3 = in.grid[2];
+  const double inv_n = 1.0 / static_cast<double>(in.npts);
+  out.assign(in.npts, 0.0);
+  for (int c1 = 0; c1 < n1; ++c1)
+    for (int c2 = 0; c2 < n2; ++c2)
+      for (int c3 = 0; c3 < n3; ++c3) {
+        double sum = 0.0;
+        int cnt = 0;
+        for (const auto& r1 : reps[0][c1])
+          for (const auto& r2 : reps[1][c2])
+            for (const auto& r3 : reps[2][c3]) {
+              const double kx = r1[0] + r2[0] + r3[0];
+              const double ky = r1[1] + r2[1] + r3[1];
+              const double kz = r1[2] + r2[2] + r3[2];
+              sum += screened(kx * kx + ky * ky + kz * kz, in.mu);
+              ++cnt;
+            }
+        out[(static_cast<size_t>(c1) * n2 + c2) * n3 + c3] = sum / cnt * inv_n;
+      }
+}
+
+size_t env_mb(const char* name, size_t dflt) {
+  const char* s = std::getenv(name);
+  if (!s || !*s) return dflt;
+  const long long v = std::atoll(s);
+  return v > 0 ? static_cast<size_t>(v) : dflt;
+}
+
+}  // namespace
+
+fock_status validate_desc(const fock_desc& d, int idx) {
+  const std::string at = "instance " + std::to_string(idx) + ": ";
+  if (!finite_all(d.lattice, 9)) return set_error(FOCK_ERR_ARG, at + "lattice not finite");
+  double nrm = 1.0;
+  for (int i = 0; i < 3; ++i)
+    nrm *= std::sqrt(d.lattice[3 * i] * d.lattice[3 * i] + d.lattice[3 * i + 1] * d.lattice[3 * i + 1] +
+                     d.lattice[3 * i + 2] * d.lattice[3 * i + 2]);
+  if (!(nrm > 0.0) || std::fabs(det3(d.lattice)) <= 1e-12 * nrm) return set_error(FOCK_ERR_ARG, at + "singular lattice");
+  for (int i = 0; i < 3; ++i) {
+    if (d.grid[i] < 2) return set_error(FOCK_ERR_ARG, at + "grid axis < 2");
+    if (d.grid[i] > kNMax || !smooth235(d.grid[i]))
+      return set_error(FOCK_ERR_UNSUPPORTED,
+                       at + "grid axis " + std::to_string(d.grid[i]) + " is not a {2,3,5}-smooth length <= 72");
+  }
+  if (d.nk < 1) return set_error(FOCK_ERR_ARG, at + "nk < 1");
+  if (!d.kfrac) return set_error(FOCK_ERR_ARG, at + "kfrac is NULL");
+  if (!finite_all(d.kfrac, 3 * d.nk)) return set_error(FOCK_ERR_ARG, at + "kfrac not finite");
+  if (d.kweight) {
+    for (int i = 0; i < d.nk; ++i)
+      if (!std::isfinite(d.kweight[i]) || d.kweight[i] < 0.0) return set_error(FOCK_ERR_ARG, at + "bad k weight");
+  }
+  if (d.npairs < 0) return set_error(FOCK_ERR_ARG, at + "npairs < 0");
+  if (d.npairs > 0) {
+    if (!d.kpairs) return set_error(FOCK_ERR_ARG, at + "kpairs is NULL");
+    for (int i = 0; i < 2 * d.npairs; ++i)
+      if (d.kpairs[i] < 0 || d.kpairs[i] >= d.nk) return set_error(FOCK_ERR_ARG, at + "k-pair index out of range");
+  }
+  if (d.nbands < 1) return set_error(FOCK_ERR_ARG, at + "nbands < 1");
+  const int64_t npts = static_cast<int64_t>(d.grid[0]) * d.grid[1] * d.grid[2];
+  if (d.band_stride < npts) return set_error(FOCK_ERR_ARG, at + "band_stride < N1*N2*N3");
+  if (!std::isfinite(d.mu) || !(d.mu > 0.0)) return set_error(FOCK_ERR_ARG, at + "mu must be finite and > 0");
+  return FOCK_OK;
+}
+
+fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, Plan** out) {
+  auto p = std::make_unique<Plan>();
+  p->prec = prec;
+  p->csize = prec == FOCK_C128 ? 16 : 8;
+  const size_t rsize = prec == FOCK_C128 ? 8 : 4;
+  p->stream = static_cast<hipStream_t>(stream);
+  p->inst.resize(n_inst);
+
+  // ---- instances, transfers and kernel tables (FP64) ----
+  std::vector<std::vector<std::vector<double>>> tables(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    const fock_desc& d = descs[i];
+    Instance& in = p->inst[i];
+    std::memcpy(in.lattice, d.lattice, sizeof(in.lattice));
+    for (int a = 0; a < 3; ++a) in.grid[a] = d.grid[a];
+    in.nk = d.nk;
+    in.kfrac.assign(d.kfrac, d.kfrac + 3 * d.nk);
+    in.kweight.resize(d.nk);
+    for (int k = 0; k < d.nk; ++k) in.kweight[k] = d.kweight ? d.kweight[k] : 1.0 / d.nk;
+    in.kpartners.assign(d.nk, {});
+    if (d.npairs == 0) {
+      for (int k = 0; k < d.nk; ++k)
+        for (int kp = 0; kp < d.nk; ++kp) in.kpartners[k].push_back(kp);
+    } else {
+      for (int e = 0; e < d.npairs; ++e) in.kpartners[d.kpairs[2 * e]].push_back(d.kpairs[2 * e + 1]);
+    }
+    std::vector<char> listed(static_cast<size_t>(d.nk) * d.nk, 0);
+    for (int k = 0; k < d.nk; ++k)
+      for (int kp : in.kpartners[k]) {
+        if (listed[static_cast<size_t>(k) * d.nk + kp])
+          return set_error(FOCK_ERR_ARG, "instance " + std::to_string(i) + ": duplicate k-pair");
+        listed[static_cast<size_t>(k) * d.nk + kp] = 1;
+      }
+    in.symmetric = true;
+    for (int k = 0; k < d.nk; ++k)
+      for (int kp = 0; kp < d.nk; ++kp)
+        if (listed[static_cast<size_t>(k) * d.nk + kp] != listed[static_cast<size_t>(kp) * d.nk + k])
+          in.symmetric = false;
+    in.nbands = d.nbands;
+    in.band_stride = d.band_stride;
+    in.mu = d.mu;
+    in.npts = static_cast<int64_t>(d.grid[0]) * d.grid[1] * d.grid[2];
+    in.omega = std::fabs(det3(d.lattice));
+    // distinct transfers q = k - k' (FP64 differences, compared bit for bit)
+    in.qmap.assign(static_cast<size_t>(d.nk) * d.nk, -1);
+    std::map<std::array<double, 3>, int> qidx;
+    for (int k = 0; k < d.nk; ++k)
+      for (int kp : in.kpartners[k]) {
+        std::array<double, 3> q = {in.kfrac[3 * k] - in.kfrac[3 * kp], in.kfrac[3 * k + 1] - in.kfrac[3 * kp + 1],
+                                   in.kfrac[3 * k + 2] - in.kfrac[3 * kp + 2]};
+        auto it = qidx.find(q);
+        int id;
+        if (it == qidx.end()) {
+          id = static_cast<int>(qidx.size());
+          qidx.emplace(q, id);
+          tables[i].emplace_back();
+          build_kernel_table(in, q.data(), tables[i].back());
+        } else {
+          id = it->second;
+        }
+        in.qmap[static_cast<size_t>(k) * d.nk + kp] = id;
+      }
+    in.nq = static_cast<int>(qidx.size());
+  }
+
+  // ---- batch shapes ----
+  const size_t tbuf_target = env_mb("FOCK_TBUF_MB", 1024) << 20;
+
+  // ---- workspace layout: constant prefix ----
+  size_t off = 0;
+  p->tw_off = off;
+  off = align_up(off + static_cast<size_t>(kTwiddleTotal) * p->csize);
+  for (auto& in : p->inst) {
+    in.vtab_off = off;
+    off = align_up(off + static_cast<size_t>(in.nq) * in.npts * rsize);
+    in.qmap_off = off;
+    off = align_up(off + in.qmap.size() * sizeof(int32_t));
+    in.kw_off = off;
+    off = align_up(off + in.kweight.size() * sizeof(double));
+  }
+  // partner lists per group of consecutive k sharing one partner list; apply batches
+  struct Group {
+    int inst, k0, k1;  // k in [k0, k1)
+    size_t off;
+    std::vector<int32_t> parts;  // (k', m) pairs
+  };
+  std::vector<Group> groups;
+  for (int i = 0; i < n_inst; ++i) {
+    const Instance& in = p->inst[i];
+    int k = 0;
+    while (k < in.nk) {
+      int k1 = k + 1;
+      while (k1 < in.nk && in.kpartners[k1] == in.kpartners[k]) ++k1;
+      Group g{i, k, k1, 0, {}};
+      for (int kp : in.kpartners[k])
+        for (int m = 0; m < in.nbands; ++m) {
+          g.parts.push_back(kp);
+          g.parts.push_back(m);
+        }
+      g.off = off;
+      off = align_up(off + g.parts.size() * sizeof(int32_t));
+      groups.push_back(std::move(g));
+      k = k1;
+    }
+  }
+  size_t max_pairs_elems = 0;  // max over batches of npairs * npts
+  for (const Group& g : groups) {
+    const Instance& in = p->inst[g.inst];
+    const int nout = (g.k1 - g.k0) * in.nbands;
+    const int npart = static_cast<int>(g.parts.size() / 2);
+    if (npart == 0) continue;
+    const size_t pair_bytes = static_cast<size_t>(in.npts) * p->csize;
+    const int pmax = static_cast<int>(std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes)));
+    int nO = std::max(1, std::min(nout, (2048 + in.grid[0] - 1) / in.grid[0]));
+    nO = std::min(nO, pmax);
+    const int nP = std::max(1, std::min(npart, pmax / nO));
+    for (int ob = 0; ob < nout; ob += nO) {
+      for (int pb = 0; pb < npart; pb += nP) {
+        Batch b;
+        b.inst = g.inst;
+        b.o0 = g.k0 * in.nbands + ob;
+        b.nO = std::min(nO, nout - ob);
+        b.part_off = g.off + static_cast<size_t>(pb) * 2 * sizeof(int32_t);
+        b.nP = std::min(nP, npart - pb);
+        b.first = pb == 0 ? 1 : 0;
+        b.npairs = b.nO * b.nP;
+        max_pairs_elems = std::max(max_pairs_elems, static_cast<size_t>(b.npairs) * in.npts);
+        p->apply_batches.push_back(b);
+        p->apply_fft_pairs += b.npairs;
+      }
+    }
+  }
+  // outputs without partners (empty k-pair list for some k) are written as zero by
+  // a dedicated apply batch with no partners: not needed, the wrapper zero-fills.
+  // energy pair lists
+  std::vector<std::vector<PairRef>> elists(n_inst);
+  size_t max_epairs = 0, max_n2 = 0;
+  int slot = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& in = p->inst[i];
+    std::vector<PairRef>& L = elists[i];
+    for (int k = 0; k < in.nk; ++k)
+      for (int n = 0; n < in.nbands; ++n)
+        for (int kp : in.kpartners[k])
+          for (int m = 0; m < in.nbands; ++m) {
+            const int a = k * in.nbands + n, bidx = kp * in.nbands + m;
+            int mult = 1;
+            if (in.symmetric) {
+              if (bidx < a) continue;
+              mult = bidx > a ? 2 : 1;
+            }
+            L.push_back(PairRef{k, n, kp, m, in.qmap[static_cast<size_t>(k) * in.nk + kp], mult});
+          }
+    for (int k = 0; k < in.nk; ++k) p->ordered_pairs += static_cast<int64_t>(in.kpartners[k].size()) * in.nbands * in.nbands;
+    const size_t pair_bytes = static_cast<size_t>(in.npts) * p->csize;
+    const size_t pmax = std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes));
+    in.first_ebatch = slot;
+    in.n_ebatches = 0;
+    const size_t base = off;
+    off = align_up(off + L.size() * sizeof(PairRef));
+    for (size_t s0 = 0; s0 < L.size(); s0 += pmax) {
+      Batch b;
+      b.inst = i;
+      b.pair_off = base + s0 * sizeof(PairRef);
+      b.npairs = static_cast<int32_t>(std::min(pmax, L.size() - s0));
+      b.slot = slot++;
+      in.n_ebatches++;
+      max_epairs = std::max(max_epairs, static_cast<size_t>(b.npairs));
+      max_pairs_elems = std::max(max_pairs_elems, static_cast<size_t>(b.npairs) * in.npts);
+      p->energy_batches.push_back(b);
+      p->energy_fft_pairs += b.npairs;
+    }
+    max_n2 = std::max(max_n2, static_cast<size_t>(in.grid[1]));
+  }
+  p->const_bytes = off;
+  // ---- scratch ----
+  p->tbuf_off = off;
+  p->tbuf_bytes = max_pairs_elems * p->csize;
+  off = align_up(off + p->tbuf_bytes);
+  p->epart_off = off;
+  p->epart_bytes = max_epairs * max_n2 * sizeof(double);
+  off = align_up(off + p->epart_bytes);
+  p->ebsum_off = off;
+  p->ebsum_bytes = static_cast<size_t>(std::max(slot, 1)) * sizeof(double);
+  off = align_up(off + p->ebsum_bytes);
+  p->total_bytes = off;
+  for (const auto& in : p->inst) {
+    const size_t plane = static_cast<size_t>(in.grid[1]) * in.grid[2], tile = static_cast<size_t>(in.grid[0]) * in.grid[2];
+    p->lds_needed = std::max(p->lds_needed, std::max(plane, tile) * p->csize + 64);
+  }
+  p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size());
+
+  // ---- host image of the constant prefix ----
+  p->host_image.assign(p->const_bytes, 0);
+  unsigned char* img = p->host_image.data();
+  for (int L = 2; L <= kNMax; ++L) {
+    if (!smooth235(L)) continue;
+    const int o = twiddle_offset(L);
+    for (int t = 0; t < L; ++t) {
+      // exp(-2 pi i t/L) in FP64, rounded once
+      const double ang = -2.0 * M_PI * static_cast<double>(t) / static_cast<double>(L);
+      const double c = std::cos(ang), s = std::sin(ang);
+      if (prec == FOCK_C128) {
+        double* w = reinterpret_cast<double*>(img + p->tw_off) + 2 * (o + t);
+        w[0] = c;
+        w[1] = s;
+      } else {
+        float* w = reinterpret_cast<float*>(img + p->tw_off) + 2 * (o + t);
+        w[0] = static_cast<float>(c);
+        w[1] = static_cast<float>(s);
+      }
+    }
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& in = p->inst[i];
+    for (int q = 0; q < in.nq; ++q) {
+      const std::vector<double>& t = tables[i][q];
+      if (prec == FOCK_C128) {
+        std::memcpy(img + in.vtab_off + static_cast<size_t>(q) * in.npts * 8, t.data(), t.size() * 8);
+      } else {
+        float* dst = reinterpret_cast<float*>(img + in.vtab_off) + static_cast<size_t>(q) * in.npts;
+        for (size_t e = 0; e < t.size(); ++e) dst[e] = static_cast<float>(t[e]);
+      }
+    }
+    std::vector<int32_t> qm(in.qmap.begin(), in.qmap.end());
+    std::memcpy(img + in.qmap_off, qm.data(), qm.size() * sizeof(int32_t));
+    std::memcpy(img + in.kw_off, in.kweight.data(), in.kweight.size() * sizeof(double));
+    tables[i].clear();
+  }
+  for (const Group& g : groups) std::memcpy(img + g.off, g.parts.data(), g.parts.size() * sizeof(int32_t));
+  for (int i = 0; i < n_inst; ++i) {
+    const Instance& in = p->inst[i];
+    if (in.n_ebatches == 0) continue;
+    const size_t base = p->energy_batches[in.first_ebatch].pair_off;
+    std::memcpy(img + base, elists[i].data(), elists[i].size() * sizeof(PairRef));
+  }
+  *out = p.release();
+  return FOCK_OK;
+}
+
+}  // namespace fock

@@ -1,0 +1,283 @@
+"""Python binding of libfock.so: argument marshalling only.
+
+Every step of the exchange path runs in the library's HIP kernels; this
+module turns torch tensors into device pointers, keeps the workspace alive
+and exposes the C ABI under the same names (fock_plan, fock_apply,
+fock_energy, fock_energy_backward).  PyTorch supplies device memory and the
+stream.  If the library is not built the calls raise: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfock.so")
+
+FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FOCK_ERR_STATE = range(6)
+FOCK_C128, FOCK_C64 = 0, 1
+
+EXPORTED = ["fock_plan", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
+            "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_destroy", "fock_status_string",
+            "fock_last_error"]
+
+
+class FockError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class FockDesc(ctypes.Structure):
+    _fields_ = [
+        ("lattice", c_double * 9),
+        ("grid", c_int32 * 3),
+        ("nk", c_int32),
+        ("kfrac", POINTER(c_double)),
+        ("kweight", POINTER(c_double)),
+        ("npairs", c_int32),
+        ("kpairs", POINTER(c_int32)),
+        ("nbands", c_int32),
+        ("band_stride", c_int64),
+        ("mu", c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfock.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.fock_plan.argtypes = [POINTER(FockDesc), c_int32, c_int, c_void_p, POINTER(c_void_p)]
+        L.fock_workspace_size.argtypes = [c_void_p, POINTER(c_size_t)]
+        L.fock_set_workspace.argtypes = [c_void_p, c_void_p, c_size_t]
+        L.fock_set_stream.argtypes = [c_void_p, c_void_p]
+        L.fock_apply.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p)]
+        L.fock_energy.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]
+        L.fock_energy_backward.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_double,
+                                           POINTER(c_void_p)]
+        L.fock_plan_stats.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
+                                      POINTER(c_int64)]
+        L.fock_destroy.argtypes = [c_void_p]
+        L.fock_status_string.argtypes = [c_int]
+        L.fock_status_string.restype = c_char_p
+        L.fock_last_error.argtypes = []
+        L.fock_last_error.restype = c_char_p
+        for name in EXPORTED:
+            if name not in ("fock_status_string", "fock_last_error"):
+                getattr(L, name).restype = c_int
+        _lib = L
+    return _lib
+
+
+def check(status):
+    if status != FOCK_OK:
+        L = lib()
+        detail = L.fock_last_error().decode()
+        raise FockError(status, f"{L.fock_status_string(status).decode()}: {detail}")
+
+
+def _ptrs(values):
+    arr = (c_void_p * len(values))()
+    for i, v in enumerate(values):
+        arr[i] = v
+    return arr
+
+
+def make_desc(lattice, grid, kfrac, kweight=None, nbands=1, band_stride=None, mu=0.106, kpairs=None, keep=None):
+    """Fill a FockDesc; host arrays are appended to ``keep`` so they outlive fock_plan."""
+    keep = keep if keep is not None else []
+    d = FockDesc()
+    lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+    for i in range(9):
+        d.lattice[i] = float(lat[i])
+    for i in range(3):
+        d.grid[i] = int(grid[i])
+    kf = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, 3))
+    keep.append(kf)
+    d.nk = kf.shape[0]
+    d.kfrac = kf.ctypes.data_as(POINTER(c_double))
+    if kweight is not None:
+        kw = np.ascontiguousarray(np.asarray(kweight, dtype=np.float64))
+        keep.append(kw)
+        d.kweight = kw.ctypes.data_as(POINTER(c_double))
+    if kpairs is not None:
+        kp = np.ascontiguousarray(np.asarray(kpairs, dtype=np.int32).reshape(-1, 2))
+        keep.append(kp)
+        d.npairs = kp.shape[0]
+        d.kpairs = kp.ctypes.data_as(POINTER(c_int32))
+    d.nbands = int(nbands)
+    n = int(grid[0]) * int(grid[1]) * int(grid[2])
+    d.band_stride = int(band_stride if band_stride is not None else n)
+    d.mu = float(mu)
+    return d
+
+
+class Plan:
+    """A plan over one or more instances, its workspace and its stream.
+
+    ``instances``: objects with lattice, grid, kfrac, kweight, nbands, mu
+    (e.g. paper_1111_0716_amd.inputs.Instance) or dicts with those keys.
+    ``precision``: "c64" (FP32 path) or "c128" (FP64 path)."""
+
+    def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None):
+        import torch
+
+        self.torch = torch
+        if not isinstance(instances, (list, tuple)):
+            instances = [instances]
+        self.precision = precision
+        self.prec = FOCK_C64 if precision == "c64" else FOCK_C128
+        self.cdtype = torch.complex64 if precision == "c64" else torch.complex128
+        self.device = torch.device(device or "cuda:0")
+        self.stream = stream
+        keep = []
+        descs = (FockDesc * len(instances))()
+        self.meta = []
+        for i, inst in enumerate(instances):
+            g = _get(inst, "grid")
+            nb = _get(inst, "nbands")
+            kp = kpairs[i] if kpairs is not None else _get(inst, "kpairs", None)
+            descs[i] = make_desc(_get(inst, "lattice"), g, _get(inst, "kfrac"), _get(inst, "kweight", None), nb,
+                                 None, _get(inst, "mu", 0.106), kp, keep)
+            lat = np.asarray(_get(inst, "lattice"), dtype=np.float64).reshape(3, 3)
+            n = int(np.prod(g))
+            self.meta.append(dict(nk=descs[i].nk, nbands=nb, npts=n, omega=abs(float(np.linalg.det(lat)))))
+        handle = c_void_p()
+        check(lib().fock_plan(descs, len(instances), self.prec, c_void_p(self._stream_ptr()), ctypes.byref(handle)))
+        self.handle = handle
+        size = c_size_t()
+        check(lib().fock_workspace_size(self.handle, ctypes.byref(size)))
+        self.workspace_bytes = size.value
+        self.workspace = torch.empty(max(size.value, 256), dtype=torch.uint8, device=self.device)
+        check(lib().fock_set_workspace(self.handle, c_void_p(self.workspace.data_ptr()), size.value))
+
+    def _stream_ptr(self):
+        if self.stream is not None:
+            return int(self.stream.cuda_stream)
+        return int(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _sync_stream(self):
+        check(lib().fock_set_stream(self.handle, c_void_p(self._stream_ptr())))
+
+    def _check_psi(self, psi, i):
+        m = self.meta[i]
+        t = self.torch
+        if not (psi.is_cuda and psi.dtype == self.cdtype and psi.is_contiguous()):
+            raise ValueError(f"psi[{i}] must be a contiguous {self.cdtype} CUDA tensor")
+        if tuple(psi.shape[:2]) != (m["nk"], m["nbands"]) or psi[0, 0].numel() != m["npts"]:
+            raise ValueError(f"psi[{i}] has shape {tuple(psi.shape)}, expected ({m['nk']}, {m['nbands']}, {m['npts']})")
+
+    def _check_occ(self, occ, i):
+        m = self.meta[i]
+        if not (occ.is_cuda and occ.dtype == self.torch.float64 and occ.is_contiguous() and
+                tuple(occ.shape) == (m["nk"], m["nbands"])):
+            raise ValueError(f"occ[{i}] must be a contiguous float64 CUDA tensor of shape ({m['nk']}, {m['nbands']})")
+
+    def fock_apply(self, psi, occ, out=None, vmat=False):
+        """V_x psi for every instance; returns (outputs, overlaps or None)."""
+        psi, occ = _aslist(psi), _aslist(occ)
+        for i, (p, o) in enumerate(zip(psi, occ)):
+            self._check_psi(p, i)
+            self._check_occ(o, i)
+        out = [self.torch.empty_like(p) for p in psi] if out is None else _aslist(out)
+        mats = None
+        if vmat:
+            mats = [self.torch.empty((m["nk"], m["nbands"], m["nbands"]), dtype=self.cdtype, device=self.device)
+                    for m in self.meta]
+        self._sync_stream()
+        check(lib().fock_apply(self.handle, _ptrs([p.data_ptr() for p in psi]), _ptrs([o.data_ptr() for o in occ]),
+                               _ptrs([x.data_ptr() for x in out]),
+                               _ptrs([x.data_ptr() for x in mats]) if mats else None))
+        return out, mats
+
+    def fock_energy(self, psi, occ, ex=None):
+        psi, occ = _aslist(psi), _aslist(occ)
+        for i, (p, o) in enumerate(zip(psi, occ)):
+            self._check_psi(p, i)
+            self._check_occ(o, i)
+        if ex is None:
+            ex = self.torch.empty(len(psi), dtype=self.torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().fock_energy(self.handle, _ptrs([p.data_ptr() for p in psi]), _ptrs([o.data_ptr() for o in occ]),
+                                c_void_p(ex.data_ptr())))
+        return ex
+
+    def fock_energy_backward(self, psi, occ, grad_ex, scale, out=None):
+        psi, occ = _aslist(psi), _aslist(occ)
+        for i, (p, o) in enumerate(zip(psi, occ)):
+            self._check_psi(p, i)
+            self._check_occ(o, i)
+        g = grad_ex.to(device=self.device, dtype=self.torch.float64).contiguous().reshape(-1)
+        out = [self.torch.empty_like(p) for p in psi] if out is None else _aslist(out)
+        self._sync_stream()
+        check(lib().fock_energy_backward(self.handle, _ptrs([p.data_ptr() for p in psi]),
+                                         _ptrs([o.data_ptr() for o in occ]), c_void_p(g.data_ptr()),
+                                         float(scale), _ptrs([x.data_ptr() for x in out])))
+        return out
+
+    def stats(self):
+        a, b, c, d = c_int64(), c_int64(), c_int64(), c_int64()
+        check(lib().fock_plan_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        return dict(ordered_pairs=a.value, apply_fft_pairs=b.value, energy_fft_pairs=c.value, apply_launches=d.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().fock_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _get(obj, key, default=KeyError):
+    if isinstance(obj, dict):
+        if key in obj:
+            return obj[key]
+    elif hasattr(obj, key):
+        return getattr(obj, key)
+    if default is KeyError:
+        raise KeyError(key)
+    return default
+
+
+def _aslist(x):
+    return list(x) if isinstance(x, (list, tuple)) else [x]
+
+
+def fock_energy_autograd():
+    """torch.autograd.Function whose forward is E_x (library fock_energy) and
+    whose backward is the library's hand-written gradient kernel path
+    (fock_energy_backward), with co-densities recomputed."""
+    import torch
+
+    class FockEnergy(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, psi, occ, plan):
+            ex = plan.fock_energy(psi, occ)
+            ctx.save_for_backward(psi, occ)
+            ctx.plan = plan
+            return ex[0]
+
+        @staticmethod
+        def backward(ctx, grad):
+            psi, occ = ctx.saved_tensors
+            plan = ctx.plan
+            m = plan.meta[0]
+            # torch's complex gradient is 2 dE/d conj(psi); dE/d conj(psi) = dV w f V_x psi
+            scale = 2.0 * m["omega"] / m["npts"]
+            g = plan.fock_energy_backward(psi, occ, grad.reshape(1), scale)[0]
+            return g, None, None
+
+    return FockEnergy

@@ -1,0 +1,175 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (relative):  FP64 path  E_x and V_x psi <= 1e-12;
+                        FP32 path  E_x <= 1e-6, V_x psi <= 1e-5 per band,
+with the oracle run on the exact complex64 values upcast to complex128.
+V_x psi error per band: ||delta||_2 / ||V_x psi||_2, max over (k, n).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.fock_oracle import Oracle
+from paper_1111_0716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": dict(e=1e-12, v=1e-12), "c64": dict(e=1e-6, v=1e-5)}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def band_err(got, ref, bands=None):
+    got = got.reshape(ref.shape)
+    err = 0.0
+    nk, nb = ref.shape[:2]
+    for k in range(nk):
+        for n in range(nb):
+            if bands is not None and (k, n) not in bands:
+                continue
+            den = np.linalg.norm(ref[k, n])
+            if den == 0:
+                err = max(err, np.linalg.norm(got[k, n]))
+            else:
+                err = max(err, np.linalg.norm(got[k, n] - ref[k, n]) / den)
+    return err
+
+
+def run_gpu(inst, prec, device, kpairs=None, vmat=False):
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    plan = fock.Plan([inst], precision=prec, device=device, kpairs=[kpairs] if kpairs is not None else None)
+    dt = np.complex64 if prec == "c64" else np.complex128
+    psi = torch.from_numpy(np.ascontiguousarray(inst.psi.astype(dt))).to(device)
+    occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
+    (vx,), mats = plan.fock_apply([psi], [occ], vmat=vmat)
+    ex = plan.fock_energy([psi], [occ])
+    torch.cuda.synchronize()
+    out = dict(vx=vx.cpu().numpy(), ex=float(ex.item()), plan=plan, psi=psi, occ=occ)
+    if vmat:
+        out["vmat"] = mats[0].cpu().numpy()
+    return out
+
+
+CASES = [
+    # grid, k-mesh, bands, full-grid orbitals, precision
+    ((16, 16, 16), (1, 1, 1), 8, False, "c128"),
+    ((12, 10, 9), (2, 1, 1), 3, False, "c128"),
+    ((24, 20, 18), (2, 1, 1), 5, False, "c128"),
+    ((8, 6, 10), (2, 2, 1), 3, True, "c128"),
+    ((72, 6, 8), (1, 1, 1), 2, True, "c128"),
+    ((6, 72, 5), (1, 1, 1), 2, True, "c128"),
+    ((5, 6, 72), (1, 2, 1), 2, True, "c128"),
+    ((48, 40, 36), (1, 1, 1), 2, False, "c128"),
+    ((27, 25, 32), (1, 1, 2), 3, False, "c128"),
+    ((24, 20, 18), (2, 1, 1), 5, False, "c64"),
+    ((16, 30, 15), (1, 2, 1), 4, False, "c64"),
+    ((8, 6, 10), (2, 2, 1), 3, True, "c64"),
+    ((64, 64, 64), (1, 1, 1), 2, False, "c64"),
+    ((72, 72, 72), (1, 1, 1), 1, False, "c64"),
+]
+
+
+@pytest.mark.parametrize("grid,kmesh,nb,full,prec", CASES)
+def test_apply_and_energy_match_oracle(grid, kmesh, nb, full, prec, device):
+    log(f"case grid={grid} kmesh={kmesh} nb={nb} full={full} prec={prec}")
+    inst = inputs.small_instance(grid=grid, kmesh=kmesh, nbands=nb, seed=(200, sum(grid)), full_grid=full)
+    if prec == "c64":
+        inst = inst.astype(np.complex64)
+    g = run_gpu(inst, prec, device, vmat=True)
+    o = Oracle.from_instance(inst)
+    vref, eref = o.apply(inst.psi.astype(np.complex128), inst.occ)
+    ev = band_err(g["vx"], vref)
+    ee = abs(g["ex"] - eref) / abs(eref)
+    log(f"  V_x err {ev:.3e}  E_x err {ee:.3e}")
+    assert ev <= TOL[prec]["v"]
+    assert ee <= TOL[prec]["e"]
+    mref = o.overlap(inst.psi.astype(np.complex128), vref)
+    em = np.max(np.abs(g["vmat"] - mref)) / np.max(np.abs(mref))
+    assert em <= TOL[prec]["v"]
+
+
+def test_plane_wave_closed_form_on_gpu(device):
+    """Golden closed form (one band at G=0, cubic 10 bohr, Gamma): E_x = -v(0)/(2 Omega)."""
+    lat = inputs.cubic_lattice(10.0)
+    grid = (16, 16, 16)
+    psi = np.full((1, 1, 4096), 1.0 / np.sqrt(1000.0), dtype=np.complex128)
+    inst = inputs.Instance(lat, grid, np.zeros((1, 3)), np.ones(1), np.ones((1, 1)), psi)
+    g = run_gpu(inst, "c128", device)
+    assert g["ex"] == pytest.approx(-0.13980031388349026, rel=1e-13)
+
+
+def test_explicit_k_pairs_and_empty_partner_lists(device):
+    inst = inputs.small_instance(grid=(12, 10, 9), kmesh=(2, 2, 1), nbands=3, seed=(201, 0))
+    kp = np.array([[0, 0], [0, 1], [1, 3], [2, 2], [2, 0]], dtype=np.int32)  # k=3 has no partner
+    g = run_gpu(inst, "c128", device, kpairs=kp)
+    o = Oracle.from_instance(inst, kpairs=kp)
+    vref, eref = o.apply(inst.psi, inst.occ)
+    assert band_err(g["vx"], vref) <= 1e-12
+    assert np.all(g["vx"].reshape(vref.shape)[3] == 0)
+    assert abs(g["ex"] - eref) <= 1e-12 * abs(eref)
+
+
+def test_fp64_results_are_bitwise_reproducible(device):
+    import torch
+
+    inst = inputs.small_instance(grid=(12, 10, 9), kmesh=(2, 1, 1), nbands=3, seed=(202, 0))
+    g = run_gpu(inst, "c128", device)
+    plan, psi, occ = g["plan"], g["psi"], g["occ"]
+    (vx2,), _ = plan.fock_apply([psi], [occ])
+    ex2 = plan.fock_energy([psi], [occ])
+    torch.cuda.synchronize()
+    assert np.array_equal(vx2.cpu().numpy(), g["vx"])
+    assert ex2.item() == g["ex"]
+
+
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_backward_matches_oracle_gradient(prec, device):
+    import torch
+
+    inst = inputs.small_instance(grid=(10, 12, 9), kmesh=(2, 1, 1), nbands=3, seed=(203, 0), full_grid=True)
+    if prec == "c64":
+        inst = inst.astype(np.complex64)
+    g = run_gpu(inst, prec, device)
+    plan, psi, occ = g["plan"], g["psi"], g["occ"]
+    o = Oracle.from_instance(inst)
+    gref = o.gradient(inst.psi.astype(np.complex128), inst.occ)  # torch convention
+    scale = 2.0 * o.dv
+    gex = torch.full((1,), 0.75, dtype=torch.float64, device=device)
+    (gg,) = plan.fock_energy_backward([psi], [occ], gex, scale)
+    torch.cuda.synchronize()
+    err = band_err(gg.cpu().numpy(), 0.75 * gref)
+    assert err <= TOL[prec]["v"]
+
+
+def test_autograd_function_and_finite_differences(device):
+    """FockEnergy forward = E_x, backward = the library gradient; FP64 central
+    differences (h = 1e-6) along random directions."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    inst = inputs.small_instance(grid=(12, 10, 9), kmesh=(1, 1, 1), nbands=4, seed=(204, 0))
+    plan = fock.Plan([inst], precision="c128", device=device)
+    FockEnergy = fock.fock_energy_autograd()
+    psi = torch.from_numpy(inst.psi).to(device).requires_grad_(True)
+    occ = torch.from_numpy(inst.occ).to(device)
+    e = FockEnergy.apply(psi, occ, plan)
+    e.backward()
+    grad = psi.grad.detach()
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    for _ in range(4):
+        d = rng.standard_normal(inst.psi.shape) + 1j * rng.standard_normal(inst.psi.shape)
+        d = torch.from_numpy(d / np.linalg.norm(d)).to(device)
+        with torch.no_grad():
+            ep = plan.fock_energy([psi.detach() + h * d], [occ]).item()
+            em = plan.fock_energy([psi.detach() - h * d], [occ]).item()
+        fd = (ep - em) / (2 * h)
+        an = torch.real(torch.vdot(grad.reshape(-1), d.reshape(-1))).item()
+        assert abs(fd - an) <= 1e-8 * torch.linalg.norm(grad).item()
