@@ -1,0 +1,251 @@
+"""Benchmark of the exchange hot path on one MI355X.
+
+Workload: the alpha-boron-shaped cell (rhombohedral a = 9.56 bohr, 58.0 deg),
+32^3 grid, uniform 4x4x4 k-mesh with all 64 k' per k (343 distinct
+transfers), 18 bands, screened kernel mu = 0.106 bohr^-1; seeded random
+orthonormal orbitals (12 Ha cutoff).  1,327,104 ordered band pairs.
+
+A step is one pass of the whole path over that input: fock_apply with the
+band overlap M (co-density, FFTs, kernel multiply, accumulate, overlap),
+fock_energy (E_x) and fock_energy_backward (dE_x/dpsi*).  `value` counts
+ordered band pairs per step divided by the step time; the FP32 (complex64)
+path is the headline, the FP64 path is reported beside it.
+
+Per-kernel times come from HIP events the library records on its own
+stream around every launch (a separate profiled step, after the timed
+steps).  The CPU baseline is the FP64 oracle timed on a bounded sample of
+pairs of the same workload on this host.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Vector ALU peak without packed FP32 math: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz.
+VALU_PEAK_TFLOPS = {"c64": 78.6, "c128": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_model(grid, s):
+    """Algorithmic flops and bytes per band pair for each apply kernel.
+
+    flops: the FFT count 5 N log2(L) per transformed axis set plus the
+    pointwise work (co-density 6N, kernel multiply 2N, accumulate 8N); the
+    three kernels sum to 10 N log2 N + 16 N.
+    bytes: what each kernel must read and write once (complex size s):
+    plane reads both orbitals and writes the pair grid, pencil reads and
+    writes it (plus one table read of 4N or 8N bytes), accumulate reads the
+    pair grid and the partner orbital (its one read-modify-write of the
+    output per batch of partners is amortised and left out)."""
+    n1, n2, n3 = grid
+    n = n1 * n2 * n3
+    r = s // 2
+    l23 = math.log2(n2 * n3)
+    l1 = math.log2(n1)
+    return {
+        "plane": dict(flops=5 * n * l23 + 6 * n, bytes=3 * s * n),
+        "pencil": dict(flops=10 * n * l1 + 2 * n, bytes=2 * s * n + r * n),
+        "accumulate": dict(flops=5 * n * l23 + 8 * n, bytes=2 * s * n),
+    }
+
+
+def run_path(inst, prec, steps, warmup, device, profile=True):
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    dt = np.complex64 if prec == "c64" else np.complex128
+    psi = torch.from_numpy(np.ascontiguousarray(inst.psi.astype(dt))).to(device)
+    occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
+    plan = fock.Plan([inst], precision=prec, device=device)
+    st = plan.stats()
+    out = torch.empty_like(psi)
+    grad = torch.empty_like(psi)
+    m = plan.meta[0]
+    gex = torch.ones(1, dtype=torch.float64, device=device)
+    scale = 2.0 * m["omega"] / m["npts"]
+
+    def step():
+        plan.fock_apply([psi], [occ], out=[out], vmat=True)
+        ex = plan.fock_energy([psi], [occ])
+        plan.fock_energy_backward([psi], [occ], gex, scale, out=[grad])
+        return ex
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        ex = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    res = dict(ms_per_step=ms, wall_s=wall, stats=st, ex=float(ex.item()))
+    if profile:
+        plan.profile(True)
+        step()
+        torch.cuda.synchronize()
+        res["kernels"] = plan.profile_read()
+        plan.profile(False)
+        # apply-only timing (one call) for the breakdown
+        t = plan.profile_read()  # reset
+        plan.profile(True)
+        plan.fock_apply([psi], [occ], out=[out], vmat=False)
+        torch.cuda.synchronize()
+        res["apply_kernels"] = plan.profile_read()
+        plan.profile(False)
+    plan.close()
+    del psi, occ, out, grad
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(inst, seconds):
+    """FP64 oracle on a bounded sample: all partners (k', m) of outputs
+    (k=0, n), in order, until `seconds` of CPU time have passed."""
+    from oracle.fock_oracle import Oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    psi = inst.psi.astype(np.complex128)
+    o = Oracle.from_instance(inst)
+    npairs = 0
+    t0 = time.perf_counter()
+    done = False
+    for n in range(inst.nbands):
+        for kp in range(inst.nk):
+            v = o.v(0, kp)
+            for m in range(inst.nbands):
+                o.pair(psi[0, n], psi[kp, m], v)
+                npairs += 1
+            if time.perf_counter() - t0 > seconds:
+                done = True
+                break
+        if done:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=npairs / el, unit="ordered band pairs/s (apply+energy per pair, FP64)", cores=threads,
+                kind="oracle", sample=f"{npairs} ordered pairs (outputs k=0, n<= {n}; every k', m) in {el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              f"(the exchange path of this library runs on a single device).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1111_0716_amd import inputs
+
+    device = torch.device("cuda:0")
+    log("generating inputs: alpha-boron-shaped 32^3, 4x4x4 k-mesh, 18 bands")
+    inst = inputs.config("2", dtype=np.complex128, workers=8)
+    inst32 = inst.astype(np.complex64)
+
+    log(f"FP32 path: {args.warmup} warm-up + {args.steps} timed steps")
+    r32 = run_path(inst32, "c64", args.steps, args.warmup, device)
+    log(f"  {r32['ms_per_step']:.2f} ms/step")
+    r64 = None
+    if not args.no_fp64:
+        k64 = args.fp64_steps or max(1, args.steps)
+        log(f"FP64 path: {args.warmup} warm-up + {k64} timed steps")
+        r64 = run_path(inst, "c128", k64, args.warmup, device)
+        log(f"  {r64['ms_per_step']:.2f} ms/step")
+
+    pairs = r32["stats"]["ordered_pairs"]
+    value = pairs / (r32["ms_per_step"] / 1e3)
+
+    # roofline of the dominant apply kernel (FP32 path)
+    n = inst.npoints
+    fft_pairs = r32["stats"]["apply_fft_pairs"]
+    kern = r32["kernels"]
+    dom = max(("plane", "pencil", "accumulate"), key=lambda k: kern[k][0])
+    launches = kern[dom][1]
+    # the profiled step runs the apply kernels twice (apply and backward)
+    units = 2 * fft_pairs
+    model = kernel_model(inst.grid, 8)
+    per_launch_ms = kern[dom][0] / max(launches, 1)
+    flops = model[dom]["flops"] * units / launches
+    byts = model[dom]["bytes"] * units / launches
+    tflops = flops / (per_launch_ms * 1e-3) / 1e12
+    gbs = byts / (per_launch_ms * 1e-3) / 1e9
+    alu_frac = tflops / VALU_PEAK_TFLOPS["c64"]
+    hbm_frac = gbs / HBM_PEAK_GBS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": VALU_PEAK_TFLOPS["c64"], "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    roof.update({"kernel": dom, "traffic": None, "launch_ms": round(per_launch_ms, 4),
+                 "alt": {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "alu_tflops": round(tflops, 3),
+                         "alu_frac": round(alu_frac, 4)}})
+
+    line = {
+        "metric": "band-pair Fock applications/s, FP32 vs FP64 path, + % of HBM roofline",
+        "value": round(value, 1),
+        "unit": "ordered band pairs/s (apply + overlap + energy + backward per step)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64 (fp32 complex)",
+        "data": "synthetic (seeded random orthonormal orbitals, 12 Ha cutoff)",
+        "config": {"workload": "alpha-boron-shaped rhombohedral cell a=9.56 bohr alpha=58.0 deg, 32^3 grid, "
+                               "4x4x4 k-mesh (all 64 k' per k), 18 bands f=1, mu=0.106",
+                   "ordered_pairs_per_step": pairs, "grid": list(inst.grid), "nk": inst.nk, "nbands": inst.nbands},
+        "roofline": roof,
+        "fp32": {"ms_per_step": round(r32["ms_per_step"], 3), "pairs_per_s": round(value, 1),
+                 "kernels_ms": {k: round(v[0], 3) for k, v in r32["kernels"].items() if v[1]},
+                 "apply_ms": round(sum(v[0] for v in r32["apply_kernels"].values()), 3)},
+    }
+    if r64:
+        v64 = pairs / (r64["ms_per_step"] / 1e3)
+        line["fp64"] = {"ms_per_step": round(r64["ms_per_step"], 3), "pairs_per_s": round(v64, 1),
+                        "kernels_ms": {k: round(v[0], 3) for k, v in r64["kernels"].items() if v[1]},
+                        "apply_ms": round(sum(v[0] for v in r64["apply_kernels"].values()), 3)}
+        line["fp32_speedup_over_fp64"] = round(r64["ms_per_step"] / r32["ms_per_step"], 3)
+        line["ex_fp32_vs_fp64_rel"] = abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])
+    if not args.no_cpu_baseline:
+        log(f"CPU baseline: FP64 oracle for ~{args.cpu_seconds:.0f} s")
+        cb = cpu_baseline(inst, args.cpu_seconds)
+        line["cpu_baseline"] = cb
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

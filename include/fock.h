@@ -129,6 +129,26 @@ fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const
 fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* apply_fft_pairs,
                             int64_t* energy_fft_pairs, int64_t* apply_launches);
 
+/* Kernel kinds for per-kernel timing. */
+typedef enum {
+  FOCK_K_PLANE = 0,          /* apply: co-density + forward FFT of axes 3, 2       */
+  FOCK_K_PENCIL = 1,         /* apply: FFT of axis 1, x v_q, inverse FFT of axis 1 */
+  FOCK_K_ACCUMULATE = 2,     /* apply: inverse FFT of axes 2, 3 + accumulate       */
+  FOCK_K_ENERGY_PLANE = 3,   /* energy: co-density + forward FFT of axes 3, 2      */
+  FOCK_K_ENERGY_PENCIL = 4,  /* energy: FFT of axis 1 + FP64 sum of v_q |P|^2      */
+  FOCK_K_ENERGY_REDUCE = 5,  /* energy: fixed-order reductions                     */
+  FOCK_K_OVERLAP = 6,        /* band overlap M                                     */
+  FOCK_K_OTHER = 7,          /* zero fill of outputs without partners              */
+  FOCK_K_COUNT = 8
+} fock_kernel_kind;
+
+/* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
+ * the plan stream.  fock_profile_read waits for the recorded events, returns
+ * the summed elapsed time and launch count of one kind since the last read of
+ * that kind, and resets them.  Off by default (no events are recorded). */
+fock_status fock_profile_enable(fock_plan_t plan, int enable);
+fock_status fock_profile_read(fock_plan_t plan, int kind, double* total_ms, int64_t* launches);
+
 /* Release the plan (host memory; the caller frees the workspace). NULL is a no-op. */
 fock_status fock_destroy(fock_plan_t plan);
 

@@ -23,6 +23,39 @@ fock_status validate_desc(const fock_desc& d, int idx);
 fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, Plan** out);
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
 
+hipEvent_t Profiler::next(hipStream_t s) {
+  if (used == pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    pool.push_back(e);
+  }
+  hipEvent_t e = pool[used++];
+  if (hipEventRecord(e, s) != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
+void Profiler::begin(int kind, hipStream_t s) {
+  if (!on) return;
+  const size_t a = used;
+  if (next(s)) spans[kind].push_back({a, a});
+}
+
+void Profiler::end(int kind, hipStream_t s) {
+  if (!on || spans[kind].empty()) return;
+  const size_t b = used;
+  if (next(s)) spans[kind].back().second = b;
+}
+
+void Profiler::release() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+  used = 0;
+  for (auto& v : spans) v.clear();
+}
+
 namespace {
 
 fock_status device_ok() {
@@ -219,6 +252,38 @@ fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* a
   if (apply_fft_pairs) *apply_fft_pairs = p->apply_fft_pairs;
   if (energy_fft_pairs) *energy_fft_pairs = p->energy_fft_pairs;
   if (apply_launches) *apply_launches = p->apply_launches;
+  return FOCK_OK;
+}
+
+fock_status fock_profile_enable(fock_plan_t plan, int enable) {
+  clear_error();
+  if (!plan) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  reinterpret_cast<Plan*>(plan)->prof.on = enable != 0;
+  return FOCK_OK;
+}
+
+fock_status fock_profile_read(fock_plan_t plan, int kind, double* total_ms, int64_t* launches) {
+  clear_error();
+  if (!plan || !total_ms || !launches) return set_error(FOCK_ERR_ARG, "NULL argument");
+  if (kind < 0 || kind >= FOCK_K_COUNT) return set_error(FOCK_ERR_ARG, "unknown kernel kind");
+  Profiler& pr = reinterpret_cast<Plan*>(plan)->prof;
+  double ms = 0.0;
+  int64_t n = 0;
+  for (const auto& sp : pr.spans[kind]) {
+    if (sp.second == sp.first) continue;
+    hipError_t e = hipEventSynchronize(pr.pool[sp.second]);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, pr.pool[sp.first], pr.pool[sp.second]);
+    if (e != hipSuccess) return hip_fail(e, "profile read");
+    ms += t;
+    ++n;
+  }
+  pr.spans[kind].clear();
+  bool any = false;
+  for (const auto& v : pr.spans) any = any || !v.empty();
+  if (!any) pr.used = 0;  // every recorded event has been read: recycle the pool
+  *total_ms = ms;
+  *launches = n;
   return FOCK_OK;
 }
 

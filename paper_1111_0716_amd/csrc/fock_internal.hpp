@@ -54,6 +54,18 @@ struct Instance {
   int first_ebatch = 0, n_ebatches = 0;
 };
 
+// Event-based per-kernel timing (see fock_profile_enable).
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> pool;  // reusable events
+  size_t used = 0;
+  std::vector<std::pair<size_t, size_t>> spans[FOCK_K_COUNT];  // (start, stop) pool indices
+  hipEvent_t next(hipStream_t s);
+  void begin(int kind, hipStream_t s);
+  void end(int kind, hipStream_t s);
+  void release();
+};
+
 struct Plan {
   fock_precision prec;
   size_t csize;  // sizeof(complex element)
@@ -75,6 +87,8 @@ struct Plan {
   int max_pairs_per_batch = 0;
   size_t max_lds = 0;      // per-block LDS limit of the device
   size_t lds_needed = 0;   // largest dynamic LDS of any launch (+ static)
+  mutable Profiler prof;
+  ~Plan() { prof.release(); }
 };
 
 // status helpers (thread-local last error)

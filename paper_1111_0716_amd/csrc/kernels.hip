@@ -319,13 +319,19 @@ hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const d
   C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
   const size_t lds_plane = static_cast<size_t>(g.n2) * g.n3 * sizeof(C);
   const size_t lds_tile = static_cast<size_t>(g.n1) * g.n3 * sizeof(C);
+  p.prof.begin(FOCK_K_PLANE, p.stream);
   hipLaunchKernelGGL((k_fwd_plane<T, false>), dim3(g.n1, b.npairs), dim3(kBlock), lds_plane, p.stream, g,
                      static_cast<const C*>(psi), b.o0, b.nP, parts, static_cast<const PairRef*>(nullptr), tbuf, tw);
+  p.prof.end(FOCK_K_PLANE, p.stream);
+  p.prof.begin(FOCK_K_PENCIL, p.stream);
   hipLaunchKernelGGL((k_pencil_apply<T>), dim3(g.n2, b.npairs), dim3(kBlock), lds_tile, p.stream, g, b.o0, b.nP,
                      parts, qmap, tbuf, vtab, tw);
+  p.prof.end(FOCK_K_PENCIL, p.stream);
+  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
   hipLaunchKernelGGL((k_inv_plane_acc<T>), dim3(g.n1, b.nO), dim3(kBlock), lds_plane, p.stream, g, b.o0, b.nP,
                      parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ, kw, static_cast<C*>(out),
                      b.first, gscale, hscale, backward ? 1 : 0, tw);
+  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
   return hipGetLastError();
 }
 
@@ -343,12 +349,18 @@ hipError_t energy_batch_t(const Plan& p, const Batch& b, const void* psi, const 
   double* ebsum = reinterpret_cast<double*>(p.ws + p.ebsum_off);
   const size_t lds_plane = static_cast<size_t>(g.n2) * g.n3 * sizeof(C);
   const size_t lds_tile = static_cast<size_t>(g.n1) * g.n3 * sizeof(C);
+  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
   hipLaunchKernelGGL((k_fwd_plane<T, true>), dim3(g.n1, b.npairs), dim3(kBlock), lds_plane, p.stream, g,
                      static_cast<const C*>(psi), 0, 1, static_cast<const int2*>(nullptr), pairs, tbuf, tw);
+  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
+  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
   hipLaunchKernelGGL((k_pencil_energy<T>), dim3(g.n2, b.npairs), dim3(kBlock), lds_tile, p.stream, g, pairs,
                      static_cast<const C*>(tbuf), vtab, tw, epart);
+  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
   hipLaunchKernelGGL(k_energy_batch, dim3(1), dim3(kBlock), 0, p.stream, pairs, b.npairs, g.n2,
                      static_cast<const double*>(epart), occ, kw, g.nbands, ebsum, b.slot);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
   return hipGetLastError();
 }
 
@@ -356,10 +368,12 @@ template <typename T>
 hipError_t overlap_t(const Plan& p, int inst, const void* psi, const void* vx, void* vmat) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[inst];
+  p.prof.begin(FOCK_K_OVERLAP, p.stream);
   hipLaunchKernelGGL((k_overlap<T>), dim3(in.nbands * in.nbands, in.nk), dim3(kBlock), 0, p.stream,
                      static_cast<const C*>(psi), static_cast<const C*>(vx), in.nbands,
                      static_cast<long long>(in.band_stride), static_cast<long long>(in.npts),
                      in.omega / static_cast<double>(in.npts), static_cast<C*>(vmat));
+  p.prof.end(FOCK_K_OVERLAP, p.stream);
   return hipGetLastError();
 }
 
@@ -386,8 +400,10 @@ hipError_t zero_outputs_t(const Plan& p, int inst, void* out) {
   for (int k = 0; k < in.nk; ++k) {
     if (!in.kpartners[k].empty()) continue;
     const int gx = static_cast<int>(std::min<long long>(1024, (in.npts + kBlock - 1) / kBlock));
+    p.prof.begin(FOCK_K_OTHER, p.stream);
     hipLaunchKernelGGL((k_zero_bands<T>), dim3(gx, in.nbands), dim3(kBlock), 0, p.stream, static_cast<C*>(out),
                        k * in.nbands, static_cast<long long>(in.band_stride), static_cast<long long>(in.npts));
+    p.prof.end(FOCK_K_OTHER, p.stream);
   }
   return hipGetLastError();
 }
@@ -427,9 +443,11 @@ hipError_t launch_energy_finish(const Plan& p, int inst, double* ex) {
   const Instance& in = p.inst[inst];
   // the tables hold v/N, so e = N * sum; E_x = -1/2 (Omega/N^2) * N * sum
   const double factor = -0.5 * in.omega / static_cast<double>(in.npts);
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
   hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(64), 0, p.stream,
                      reinterpret_cast<const double*>(p.ws + p.ebsum_off), in.first_ebatch, in.n_ebatches, factor,
                      ex);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
   return hipGetLastError();
 }
 

@@ -21,8 +21,10 @@ FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FO
 FOCK_C128, FOCK_C64 = 0, 1
 
 EXPORTED = ["fock_plan", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
-            "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_destroy", "fock_status_string",
-            "fock_last_error"]
+            "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_profile_enable", "fock_profile_read",
+            "fock_destroy", "fock_status_string", "fock_last_error"]
+KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
+                "other"]
 
 
 class FockError(RuntimeError):
@@ -66,6 +68,8 @@ def lib():
                                            POINTER(c_void_p)]
         L.fock_plan_stats.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
                                       POINTER(c_int64)]
+        L.fock_profile_enable.argtypes = [c_void_p, c_int]
+        L.fock_profile_read.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(c_int64)]
         L.fock_destroy.argtypes = [c_void_p]
         L.fock_status_string.argtypes = [c_int]
         L.fock_status_string.restype = c_char_p
@@ -228,6 +232,19 @@ class Plan:
         a, b, c, d = c_int64(), c_int64(), c_int64(), c_int64()
         check(lib().fock_plan_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
         return dict(ordered_pairs=a.value, apply_fft_pairs=b.value, energy_fft_pairs=c.value, apply_launches=d.value)
+
+    def profile(self, enable=True):
+        """Bracket every library launch with HIP events on the plan stream."""
+        check(lib().fock_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kind: (total_ms, launches)} since the last read; waits for the events."""
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            ms, n = c_double(), c_int64()
+            check(lib().fock_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if getattr(self, "handle", None):
