@@ -40,26 +40,61 @@ def log(*a):
 
 
 def kernel_model(grid, s):
-    """Algorithmic flops and bytes per band pair for each apply kernel.
+    """Algorithmic flops and bytes per band pair for each kernel kind.
 
-    flops: the FFT count 5 N log2(L) per transformed axis set plus the
-    pointwise work (co-density 6N, kernel multiply 2N, accumulate 8N); the
-    three kernels sum to 10 N log2 N + 16 N.
-    bytes: what each kernel must read and write once (complex size s):
-    plane reads both orbitals and writes the pair grid, pencil reads and
-    writes it (plus one table read of 4N or 8N bytes), accumulate reads the
-    pair grid and the partner orbital (its one read-modify-write of the
-    output per batch of partners is amortised and left out)."""
+    Whole-pair kernels (one band pair per pass, nothing staged off chip):
+      apply   F = 10 N log2 N + 16 N,  B = 4 s N  (read u_m and u_n, read and
+              write the output once per pair: the compulsory operand traffic)
+      energy  F = 5 N log2 N + 9 N,    B = 2 s N  (read u_m and u_n)
+    Three-pass kernels (the same flops split by pass; bytes are what each pass
+    must read and write once, its pair grid included):
+      plane       F = 5 N log2(N2 N3) + 6 N,  B = 3 s N
+      pencil      F = 10 N log2 N1 + 2 N,     B = 2 s N + r N (table)
+      accumulate  F = 5 N log2(N2 N3) + 8 N,  B = 2 s N
+    with s the complex size and r the real size."""
     n1, n2, n3 = grid
     n = n1 * n2 * n3
     r = s // 2
     l23 = math.log2(n2 * n3)
     l1 = math.log2(n1)
     return {
+        "fused": dict(flops=10 * n * math.log2(n) + 16 * n, bytes=4 * s * n),
+        "energy_fused": dict(flops=5 * n * math.log2(n) + 9 * n, bytes=2 * s * n),
         "plane": dict(flops=5 * n * l23 + 6 * n, bytes=3 * s * n),
         "pencil": dict(flops=10 * n * l1 + 2 * n, bytes=2 * s * n + r * n),
         "accumulate": dict(flops=5 * n * l23 + 8 * n, bytes=2 * s * n),
+        "energy_plane": dict(flops=5 * n * l23 + 6 * n, bytes=3 * s * n),
+        "energy_pencil": dict(flops=5 * n * l1 + 3 * n, bytes=s * n + r * n),
     }
+
+
+def roofline(kern, stats, grid, s, peak_tflops):
+    """Roofline entry of the kernel kind with the largest share of the
+    profiled step (apply, energy and backward: apply kinds run twice)."""
+    model = kernel_model(grid, s)
+    units = {k: 2 * stats["apply_fft_pairs"] for k in ("fused", "plane", "pencil", "accumulate")}
+    units.update({k: stats["energy_fft_pairs"] for k in ("energy_fused", "energy_plane", "energy_pencil")})
+    cands = [k for k in model if kern.get(k, (0, 0))[1] > 0]
+    dom = max(cands, key=lambda k: kern[k][0])
+    tot_ms, launches = kern[dom]
+    per_launch_ms = tot_ms / launches
+    flops = model[dom]["flops"] * units[dom] / launches
+    byts = model[dom]["bytes"] * units[dom] / launches
+    tflops = flops / (per_launch_ms * 1e-3) / 1e12
+    gbs = byts / (per_launch_ms * 1e-3) / 1e9
+    alu_frac = tflops / peak_tflops
+    hbm_frac = gbs / HBM_PEAK_GBS
+    if alu_frac >= hbm_frac:
+        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": peak_tflops, "unit": "TFLOP/s",
+                "frac": round(alu_frac, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4)}
+    roof.update({"traffic": None, "kernel": dom, "launches": launches, "launch_ms": round(per_launch_ms, 4),
+                 "units_per_launch": round(units[dom] / launches, 1),
+                 "alt": {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "alu_tflops": round(tflops, 3),
+                         "alu_frac": round(alu_frac, 4)}})
+    return roof
 
 
 def run_path(inst, prec, steps, warmup, device, profile=True):
@@ -186,31 +221,7 @@ def main():
     pairs = r32["stats"]["ordered_pairs"]
     value = pairs / (r32["ms_per_step"] / 1e3)
 
-    # roofline of the dominant apply kernel (FP32 path)
-    n = inst.npoints
-    fft_pairs = r32["stats"]["apply_fft_pairs"]
-    kern = r32["kernels"]
-    dom = max(("plane", "pencil", "accumulate"), key=lambda k: kern[k][0])
-    launches = kern[dom][1]
-    # the profiled step runs the apply kernels twice (apply and backward)
-    units = 2 * fft_pairs
-    model = kernel_model(inst.grid, 8)
-    per_launch_ms = kern[dom][0] / max(launches, 1)
-    flops = model[dom]["flops"] * units / launches
-    byts = model[dom]["bytes"] * units / launches
-    tflops = flops / (per_launch_ms * 1e-3) / 1e12
-    gbs = byts / (per_launch_ms * 1e-3) / 1e9
-    alu_frac = tflops / VALU_PEAK_TFLOPS["c64"]
-    hbm_frac = gbs / HBM_PEAK_GBS
-    if alu_frac >= hbm_frac:
-        roof = {"bound": "alu", "achieved": round(tflops, 3), "peak": VALU_PEAK_TFLOPS["c64"], "unit": "TFLOP/s",
-                "frac": round(alu_frac, 4)}
-    else:
-        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(hbm_frac, 4)}
-    roof.update({"kernel": dom, "traffic": None, "launch_ms": round(per_launch_ms, 4),
-                 "alt": {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "alu_tflops": round(tflops, 3),
-                         "alu_frac": round(alu_frac, 4)}})
+    roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"])
 
     line = {
         "metric": "band-pair Fock applications/s, FP32 vs FP64 path, + % of HBM roofline",

@@ -139,7 +139,9 @@ typedef enum {
   FOCK_K_ENERGY_REDUCE = 5,  /* energy: fixed-order reductions                     */
   FOCK_K_OVERLAP = 6,        /* band overlap M                                     */
   FOCK_K_OTHER = 7,          /* zero fill of outputs without partners              */
-  FOCK_K_COUNT = 8
+  FOCK_K_FUSED = 8,          /* apply: whole pair per workgroup (cubic <= 32^3)    */
+  FOCK_K_ENERGY_FUSED = 9,   /* energy: whole pair per workgroup (cubic <= 32^3)   */
+  FOCK_K_COUNT = 10
 } fock_kernel_kind;
 
 /* Per-kernel timing: when enabled, every launch is bracketed by HIP events on

@@ -101,6 +101,11 @@ fock_status run_apply(Plan* p, const void* const* psi, const double* const* occ,
       if (e != hipSuccess) return hip_fail(e, "zero outputs");
     }
   }
+  for (const FusedGroup& g : p->fused_groups) {
+    const hipError_t e = launch_fused_apply(*p, g, psi[g.inst], occ[g.inst], out[g.inst],
+                                            gscale ? gscale + g.inst : nullptr, hscale, backward);
+    if (e != hipSuccess) return hip_fail(e, "whole-pair apply launch");
+  }
   for (const Batch& b : p->apply_batches) {
     const hipError_t e = launch_apply_batch(*p, b, psi[b.inst], occ[b.inst], out[b.inst],
                                             gscale ? gscale + b.inst : nullptr, hscale, backward);
@@ -217,7 +222,13 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
   if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
   if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
   for (const Batch& b : p->energy_batches) {
-    const hipError_t e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
+    hipError_t e;
+    if (p->inst[b.inst].fused) {
+      e = launch_fused_energy(*p, b, psi[b.inst]);
+      if (e == hipSuccess) e = launch_energy_reduce(*p, b, occ[b.inst], 1);
+    } else {
+      e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
+    }
     if (e != hipSuccess) return hip_fail(e, "energy batch launch");
   }
   for (size_t i = 0; i < p->inst.size(); ++i) {

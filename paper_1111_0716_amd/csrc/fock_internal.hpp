@@ -33,6 +33,16 @@ struct Batch {
   size_t pair_off = 0;  // bytes into the workspace
   int32_t npairs = 0;   // pairs in the batch (apply: nO*nP)
   int32_t slot = 0;
+  int32_t per_wg = 1;   // energy on the whole-pair path: pairs per workgroup
+};
+
+// Outputs o0..o0+nout-1 of one instance on the whole-pair path, all sharing
+// the partner list (int2 (k', m)) at part_off.
+struct FusedGroup {
+  int32_t inst = 0;
+  int32_t o0 = 0, nout = 0;
+  size_t part_off = 0;
+  int32_t npart = 0;
 };
 
 struct Instance {
@@ -42,6 +52,7 @@ struct Instance {
   std::vector<double> kfrac, kweight;
   std::vector<std::vector<int>> kpartners;  // k -> list of k'
   bool symmetric = true;                     // (k, k') listed iff (k', k) listed
+  bool fused = false;                        // whole-pair path (cubic grid that fits one CU)
   int nbands;
   int64_t band_stride;
   double mu;
@@ -72,6 +83,7 @@ struct Plan {
   hipStream_t stream = nullptr;
   std::vector<Instance> inst;
   std::vector<Batch> apply_batches, energy_batches;
+  std::vector<FusedGroup> fused_groups;
   // workspace layout (bytes)
   size_t tw_off = 0;                  // twiddle tables
   size_t const_bytes = 0;             // uploaded prefix
@@ -102,6 +114,14 @@ hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, co
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 hipError_t launch_energy_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
+hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ, int n2);
+// whole-pair path (pair_fused.hip)
+bool fused_supported(fock_precision prec, const int grid[3]);
+size_t fused_lds_bytes(fock_precision prec, int L);
+void prepare_fused_kernels(fock_precision prec, int lim);
+hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
+                              const double* gscale, double hscale, bool backward);
+hipError_t launch_fused_energy(const Plan& p, const Batch& b, const void* psi);
 hipError_t launch_overlap(const Plan& p, int inst, const void* psi, const void* vx, void* vmat);
 
 }  // namespace fock

@@ -357,11 +357,7 @@ hipError_t energy_batch_t(const Plan& p, const Batch& b, const void* psi, const 
   hipLaunchKernelGGL((k_pencil_energy<T>), dim3(g.n2, b.npairs), dim3(kBlock), lds_tile, p.stream, g, pairs,
                      static_cast<const C*>(tbuf), vtab, tw, epart);
   p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
-  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
-  hipLaunchKernelGGL(k_energy_batch, dim3(1), dim3(kBlock), 0, p.stream, pairs, b.npairs, g.n2,
-                     static_cast<const double*>(epart), occ, kw, g.nbands, ebsum, b.slot);
-  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
-  return hipGetLastError();
+  return launch_energy_reduce(p, b, occ, g.n2);
 }
 
 template <typename T>
@@ -420,6 +416,7 @@ hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
   if (e == hipSuccess) e = hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
   *max_lds = static_cast<size_t>(lim);
+  prepare_fused_kernels(prec, lim - 256);
   if (lim > 65536) {
     if (prec == FOCK_C128)
       allow_large_lds<double>(lim - 64);
@@ -437,6 +434,18 @@ hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, co
 
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
   return p.prec == FOCK_C128 ? energy_batch_t<double>(p, b, psi, occ) : energy_batch_t<float>(p, b, psi, occ);
+}
+
+hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ, int n2) {
+  const Instance& in = p.inst[b.inst];
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
+  hipLaunchKernelGGL(k_energy_batch, dim3(1), dim3(kBlock), 0, p.stream,
+                     reinterpret_cast<const PairRef*>(p.ws + b.pair_off), b.npairs, n2,
+                     reinterpret_cast<const double*>(p.ws + p.epart_off), occ,
+                     reinterpret_cast<const double*>(p.ws + in.kw_off), in.nbands,
+                     reinterpret_cast<double*>(p.ws + p.ebsum_off), b.slot);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
+  return hipGetLastError();
 }
 
 hipError_t launch_energy_finish(const Plan& p, int inst, double* ex) {

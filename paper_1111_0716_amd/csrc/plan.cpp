@@ -209,6 +209,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       }
     in.nq = static_cast<int>(qidx.size());
   }
+  const char* nofused = std::getenv("FOCK_NO_FUSED");
+  for (auto& in : p->inst) in.fused = fused_supported(prec, in.grid) && !(nofused && *nofused && *nofused != '0');
 
   // ---- batch shapes ----
   const size_t tbuf_target = env_mb("FOCK_TBUF_MB", 1024) << 20;
@@ -256,6 +258,17 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     const int nout = (g.k1 - g.k0) * in.nbands;
     const int npart = static_cast<int>(g.parts.size() / 2);
     if (npart == 0) continue;
+    if (in.fused) {
+      FusedGroup fg;
+      fg.inst = g.inst;
+      fg.o0 = g.k0 * in.nbands;
+      fg.nout = nout;
+      fg.part_off = g.off;
+      fg.npart = npart;
+      p->fused_groups.push_back(fg);
+      p->apply_fft_pairs += static_cast<int64_t>(nout) * npart;
+      continue;
+    }
     const size_t pair_bytes = static_cast<size_t>(in.npts) * p->csize;
     const int pmax = static_cast<int>(std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes)));
     int nO = std::max(1, std::min(nout, (2048 + in.grid[0] - 1) / in.grid[0]));
@@ -281,7 +294,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   // a dedicated apply batch with no partners: not needed, the wrapper zero-fills.
   // energy pair lists
   std::vector<std::vector<PairRef>> elists(n_inst);
-  size_t max_epairs = 0, max_n2 = 0;
+  size_t max_epairs = 0, max_n2 = 0, max_fused_epairs = 0;
   int slot = 0;
   for (int i = 0; i < n_inst; ++i) {
     Instance& in = p->inst[i];
@@ -300,7 +313,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
           }
     for (int k = 0; k < in.nk; ++k) p->ordered_pairs += static_cast<int64_t>(in.kpartners[k].size()) * in.nbands * in.nbands;
     const size_t pair_bytes = static_cast<size_t>(in.npts) * p->csize;
-    const size_t pmax = std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes));
+    size_t pmax = std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes));
+    if (in.fused) pmax = std::max<size_t>(1, L.size());  // one launch; no pair buffer
     in.first_ebatch = slot;
     in.n_ebatches = 0;
     const size_t base = off;
@@ -312,8 +326,13 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       b.npairs = static_cast<int32_t>(std::min(pmax, L.size() - s0));
       b.slot = slot++;
       in.n_ebatches++;
-      max_epairs = std::max(max_epairs, static_cast<size_t>(b.npairs));
-      max_pairs_elems = std::max(max_pairs_elems, static_cast<size_t>(b.npairs) * in.npts);
+      if (in.fused) {
+        b.per_wg = std::max(1, b.npairs / 1024);
+        max_fused_epairs = std::max(max_fused_epairs, static_cast<size_t>(b.npairs));
+      } else {
+        max_epairs = std::max(max_epairs, static_cast<size_t>(b.npairs));
+        max_pairs_elems = std::max(max_pairs_elems, static_cast<size_t>(b.npairs) * in.npts);
+      }
       p->energy_batches.push_back(b);
       p->energy_fft_pairs += b.npairs;
     }
@@ -325,7 +344,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->tbuf_bytes = max_pairs_elems * p->csize;
   off = align_up(off + p->tbuf_bytes);
   p->epart_off = off;
-  p->epart_bytes = max_epairs * max_n2 * sizeof(double);
+  p->epart_bytes = std::max(max_epairs * max_n2, max_fused_epairs) * sizeof(double);
   off = align_up(off + p->epart_bytes);
   p->ebsum_off = off;
   p->ebsum_bytes = static_cast<size_t>(std::max(slot, 1)) * sizeof(double);
@@ -333,9 +352,10 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->total_bytes = off;
   for (const auto& in : p->inst) {
     const size_t plane = static_cast<size_t>(in.grid[1]) * in.grid[2], tile = static_cast<size_t>(in.grid[0]) * in.grid[2];
-    p->lds_needed = std::max(p->lds_needed, std::max(plane, tile) * p->csize + 64);
+    const size_t need = in.fused ? fused_lds_bytes(prec, in.grid[0]) + 256 : std::max(plane, tile) * p->csize + 64;
+    p->lds_needed = std::max(p->lds_needed, need);
   }
-  p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size());
+  p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size()) + static_cast<int64_t>(p->fused_groups.size());
 
   // ---- host image of the constant prefix ----
   p->host_image.assign(p->const_bytes, 0);
@@ -361,7 +381,17 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   for (int i = 0; i < n_inst; ++i) {
     Instance& in = p->inst[i];
     for (int q = 0; q < in.nq; ++q) {
-      const std::vector<double>& t = tables[i][q];
+      std::vector<double>& t = tables[i][q];
+      if (in.fused) {
+        // whole-pair path reads the table in C order: (c3*L + c2)*L + c1
+        const int L = in.grid[0];
+        std::vector<double> r(t.size());
+        for (int c1 = 0; c1 < L; ++c1)
+          for (int c2 = 0; c2 < L; ++c2)
+            for (int c3 = 0; c3 < L; ++c3)
+              r[(static_cast<size_t>(c3) * L + c2) * L + c1] = t[(static_cast<size_t>(c1) * L + c2) * L + c3];
+        t.swap(r);
+      }
       if (prec == FOCK_C128) {
         std::memcpy(img + in.vtab_off + static_cast<size_t>(q) * in.npts * 8, t.data(), t.size() * 8);
       } else {

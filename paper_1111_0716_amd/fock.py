@@ -24,7 +24,7 @@ EXPORTED = ["fock_plan", "fock_workspace_size", "fock_set_workspace", "fock_set_
             "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_profile_enable", "fock_profile_read",
             "fock_destroy", "fock_status_string", "fock_last_error"]
 KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
-                "other"]
+                "other", "fused", "energy_fused"]
 
 
 class FockError(RuntimeError):

@@ -72,6 +72,12 @@ CASES = [
     ((8, 6, 10), (2, 2, 1), 3, True, "c64"),
     ((64, 64, 64), (1, 1, 1), 2, False, "c64"),
     ((72, 72, 72), (1, 1, 1), 1, False, "c64"),
+    # whole-pair path (cubic grids that fit one compute unit)
+    ((32, 32, 32), (1, 1, 1), 3, False, "c64"),
+    ((32, 32, 32), (2, 1, 1), 2, True, "c64"),
+    ((24, 24, 24), (2, 1, 1), 3, False, "c64"),
+    ((16, 16, 16), (1, 2, 1), 3, True, "c64"),
+    ((16, 16, 16), (2, 1, 1), 3, True, "c128"),
 ]
 
 
@@ -173,3 +179,48 @@ def test_autograd_function_and_finite_differences(device):
         fd = (ep - em) / (2 * h)
         an = torch.real(torch.vdot(grad.reshape(-1), d.reshape(-1))).item()
         assert abs(fd - an) <= 1e-8 * torch.linalg.norm(grad).item()
+
+
+@pytest.mark.parametrize("grid,prec", [((32, 32, 32), "c64"), ((24, 24, 24), "c64"), ((16, 16, 16), "c128")])
+def test_whole_pair_path_matches_three_pass_path(grid, prec, device, monkeypatch):
+    """The whole-pair kernels and the three-pass kernels compute the same
+    operator: compare them directly (and both against the oracle above)."""
+    inst = inputs.small_instance(grid=grid, kmesh=(2, 1, 1), nbands=3, seed=(205, grid[0]))
+    if prec == "c64":
+        inst = inst.astype(np.complex64)
+    fused = run_gpu(inst, prec, device)
+    monkeypatch.setenv("FOCK_NO_FUSED", "1")
+    three = run_gpu(inst, prec, device)
+    assert band_err(fused["vx"], three["vx"].reshape(fused["vx"].shape)) <= 2 * TOL[prec]["v"]
+    assert abs(fused["ex"] - three["ex"]) <= 2 * TOL[prec]["e"] * abs(three["ex"])
+
+
+def test_alpha_boron_config_sampled_outputs(device):
+    """Full-size alpha-boron workload (32^3, 4x4x4 k-mesh, 18 bands) on the FP32
+    path as the benchmark runs it: sampled outputs against the oracle (every
+    partner of the sampled band), E_x against 1/2 sum w f <u|V_x u> from the
+    GPU's own apply, and E_x against the FP64 path."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    inst = inputs.config("2", dtype=np.complex128, workers=8)
+    inst32 = inst.astype(np.complex64)
+    log("config 2 FP32 full apply")
+    g = run_gpu(inst32, "c64", device, vmat=True)
+    o = Oracle.from_instance(inst32)
+    for (k, n) in [(0, 0), (37, 11), (63, 17)]:
+        vref, _ = o.apply(inst32.psi.astype(np.complex128), inst32.occ, outputs=[(k, n)])
+        err = band_err(g["vx"], vref, bands={(k, n)})
+        log(f"  output ({k},{n}) err {err:.2e}")
+        assert err <= 1e-5
+    m = g["vmat"]
+    ex_apply = 0.5 * np.sum(inst.kweight[:, None] * inst.occ * np.real(np.einsum("kii->ki", m)))
+    assert abs(ex_apply - g["ex"]) <= 1e-5 * abs(g["ex"])
+    log("config 2 FP64 energy")
+    plan64 = fock.Plan([inst], precision="c128", device=device)
+    psi64 = torch.from_numpy(inst.psi).to(device)
+    occ64 = torch.from_numpy(inst.occ).to(device)
+    ex64 = plan64.fock_energy([psi64], [occ64]).item()
+    log(f"  E32 {g['ex']:.12f}  E64 {ex64:.12f}")
+    assert abs(g["ex"] - ex64) <= 1e-6 * abs(ex64)
