@@ -43,6 +43,7 @@ struct FusedGroup {
   int32_t o0 = 0, nout = 0;
   size_t part_off = 0;
   int32_t npart = 0;
+  int32_t nsplit = 1;  // partner slices per output (slices > 0 sum into partial buffers)
 };
 
 struct Instance {
@@ -90,6 +91,7 @@ struct Plan {
   size_t tbuf_off = 0, tbuf_bytes = 0;
   size_t epart_off = 0, epart_bytes = 0;
   size_t ebsum_off = 0, ebsum_bytes = 0;
+  size_t partial_off = 0, partial_bytes = 0;
   size_t total_bytes = 0;
   std::vector<unsigned char> host_image;  // constant prefix, uploaded by set_workspace
   unsigned char* ws = nullptr;            // device workspace (caller-owned)
@@ -118,6 +120,7 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
 // whole-pair path (pair_fused.hip)
 bool fused_supported(fock_precision prec, const int grid[3]);
 size_t fused_lds_bytes(fock_precision prec, int L);
+int fused_threads(fock_precision prec, int L);
 void prepare_fused_kernels(fock_precision prec, int lim);
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
                               const double* gscale, double hscale, bool backward);

@@ -17,6 +17,8 @@
 // The kernel table is stored for this path in C order, (c3*L + c2)*L + c1, so
 // the multiply reads it coalesced.  V_x u is accumulated in registers when
 // the accumulator fits beside the line, else read-modify-written per partner.
+#include <algorithm>
+
 #include "fft_lds.hpp"
 #include "fock_internal.hpp"
 #include "twiddle_ce.hpp"
@@ -101,7 +103,44 @@ struct FusedShape {
   static constexpr int LDS = XA > XB ? XA : XB;
   // accumulate V_x u in registers when it fits beside the lines
   static constexpr bool ACC_REG = (L <= 16) || (L <= 24 && sizeof(T) == 4);
+  // 128-byte lines of one orbital and of one table, and their share per thread
+  static constexpr int ORB_LINES = (L * L * L * static_cast<int>(sizeof(C))) / 128;
+  static constexpr int TAB_LINES = (L * L * L * static_cast<int>(sizeof(T))) / 128;
+  static constexpr int PF_ORB = (ORB_LINES + NT - 1) / NT;
+  static constexpr int PF_TAB = (TAB_LINES + NT - 1) / NT;
 };
+
+// Pull the next orbital and kernel table into L2 while the FFTs run: one
+// dword of every 128-byte line is loaded with the LDS-DMA form of the load,
+// which needs no destination register.  All waves land their dwords in the
+// same dead 256-byte LDS area (`junk`); nothing ever reads it.
+typedef __attribute__((address_space(1))) const void* gptr_t;
+typedef __attribute__((address_space(3))) void* lptr_t;
+
+// What to pull into L2 during the forward transform (null orb: nothing).
+template <typename T>
+struct Prefetch {
+  const typename cx<T>::t* orb;
+  const T* tab;
+  float* junk;
+};
+
+template <typename T, int L>
+__device__ __forceinline__ void prefetch_lines(const typename cx<T>::t* orb, const T* tab, int t, float* junk) {
+  using Sh = FusedShape<T, L>;
+  const float* o = reinterpret_cast<const float*>(orb);
+  const float* b = reinterpret_cast<const float*>(tab);
+#pragma unroll
+  for (int k = 0; k < Sh::PF_ORB; ++k) {
+    const int line = t + k * Sh::NT;
+    if (line < Sh::ORB_LINES) __builtin_amdgcn_global_load_lds((gptr_t)(o + line * 32), (lptr_t)junk, 4, 0, 0);
+  }
+#pragma unroll
+  for (int k = 0; k < Sh::PF_TAB; ++k) {
+    const int line = t + k * Sh::NT;
+    if (line < Sh::TAB_LINES) __builtin_amdgcn_global_load_lds((gptr_t)(b + line * 32), (lptr_t)junk, 4, 0, 0);
+  }
+}
 
 // LDS element at a byte address (base VGPR + immediate offset when the
 // offset is a compile-time constant below 64 KiB).
@@ -181,7 +220,8 @@ __device__ __forceinline__ void xchg_ab(typename cx<T>::t (*x)[L], typename cx<T
 // thread has one line per round (LPT == NR), line l is exchanged in round l.
 // LDS layout [c2 - r*CH][c1][j3] with padded rows: ((rr*L + c1)*LP + j3).
 template <typename T, int L, bool B_TO_C>
-__device__ __forceinline__ void xchg_bc(typename cx<T>::t (*x)[L], typename cx<T>::t* sp, int row0, int col) {
+__device__ __forceinline__ void xchg_bc(typename cx<T>::t (*x)[L], typename cx<T>::t* sp, int row0, int col,
+                                        Prefetch<T> pf = Prefetch<T>{nullptr, nullptr, nullptr}) {
   using C = typename cx<T>::t;
   using Sh = FusedShape<T, L>;
   constexpr int SZ = sizeof(C);
@@ -206,6 +246,9 @@ __device__ __forceinline__ void xchg_bc(typename cx<T>::t (*x)[L], typename cx<T
       }
     }
     __syncthreads();
+    // the line just written is dead until read back: the cheapest moment to
+    // issue the L2 prefetch of the next partner
+    if (r == 0 && pf.orb) prefetch_lines<T, L>(pf.orb, pf.tab, static_cast<int>(threadIdx.x), pf.junk);
 #pragma unroll
     for (int l = 0; l < Sh::LPT; ++l) {
       const int row = row0 + l * Sh::RPT;
@@ -231,16 +274,21 @@ template <typename T, int L, int S>
 __device__ __forceinline__ void reg_fft_lines(typename cx<T>::t (*x)[L]) {
   using Sh = FusedShape<T, L>;
 #pragma unroll
-  for (int l = 0; l < Sh::LPT; ++l) reg_fft<typename cx<T>::t, L, S>(x[l]);
+  for (int l = 0; l < Sh::LPT; ++l) {
+    __builtin_amdgcn_sched_barrier(0);  // one line at a time
+    reg_fft<typename cx<T>::t, L, S>(x[l]);
+  }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // rho in layout A -> P (c1, c2, c3) in layout C
 template <typename T, int L>
-__device__ __forceinline__ void fused_forward(typename cx<T>::t (*x)[L], typename cx<T>::t* s, int row0, int col) {
+__device__ __forceinline__ void fused_forward(typename cx<T>::t (*x)[L], typename cx<T>::t* s, int row0, int col,
+                                              Prefetch<T> pf = Prefetch<T>{nullptr, nullptr, nullptr}) {
   reg_fft_lines<T, L, -1>(x);
   xchg_ab<T, L, true>(x, s, row0, col);
   reg_fft_lines<T, L, -1>(x);
-  xchg_bc<T, L, true>(x, s, row0, col);
+  xchg_bc<T, L, true>(x, s, row0, col, pf);
   reg_fft_lines<T, L, -1>(x);
 }
 
@@ -327,24 +375,33 @@ __device__ __forceinline__ void mul_kernel(typename cx<T>::t (*x)[L], const T* _
 // ---------------------------------------------------------------------------
 template <typename T, int L>
 __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
-    int nbands, long long bs, int o0, const typename cx<T>::t* __restrict__ psi, const int2* __restrict__ parts,
-    int npart, int nk, const int* __restrict__ qmap, const T* __restrict__ vtab, const double* __restrict__ occ,
-    const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, const double* __restrict__ gscale,
+    int nbands, long long bs, int o0, int nout, const typename cx<T>::t* __restrict__ psi,
+    const int2* __restrict__ parts, int npart, int nsplit, int nk, const int* __restrict__ qmap,
+    const T* __restrict__ vtab, const double* __restrict__ occ, const double* __restrict__ kw,
+    typename cx<T>::t* __restrict__ out, typename cx<T>::t* __restrict__ partial, const double* __restrict__ gscale,
     double hscale, int backward) {
   using C = typename cx<T>::t;
   using Sh = FusedShape<T, L>;
   constexpr int LL = L * L;
   constexpr int LPT = Sh::LPT;
   extern __shared__ unsigned char smem_raw[];
+  __shared__ float junk[64];  // landing area of the L2 prefetch (never read)
   C* s = reinterpret_cast<C*>(smem_raw);
   const int t = threadIdx.x, row0 = t / L, col = t - (t / L) * L;
-  const int okn = o0 + blockIdx.x;
+  // block = (output, partner slice); slice 0 writes the output, slice s > 0 a partial
+  const int oi = blockIdx.x % nout, slice = blockIdx.x / nout;
+  const int okn = o0 + oi;
   const int ok = okn / nbands;
+  const int p0 = static_cast<int>((static_cast<long long>(npart) * slice) / nsplit);
+  const int p1 = static_cast<int>((static_cast<long long>(npart) * (slice + 1)) / nsplit);
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[ok] * occ[okn];
   const size_t npts = static_cast<size_t>(LL) * L;
   const size_t on = static_cast<size_t>(okn) * bs;
+  // destination of this block's sum: the output band, or its partial slot
+  C* const dst = slice == 0 ? out : partial;
+  const size_t od = slice == 0 ? on : (static_cast<size_t>(slice - 1) * nout + oi) * npts;
   const uint32_t toff0 = static_cast<uint32_t>(row0 * LL + col);  // layout A element (j1 = row0, 0, j3 = col)
   C acc[Sh::ACC_REG ? LPT : 1][Sh::ACC_REG ? L : 1];
   if constexpr (Sh::ACC_REG) {
@@ -353,25 +410,32 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
 #pragma unroll
       for (int i = 0; i < L; ++i) acc[l][i] = C{T(0), T(0)};
   }
-  for (int p = 0; p < npart; ++p) {
+  for (int p = p0; p < p1; ++p) {
     const int2 r = parts[p];
     const int pkm = r.x * nbands + r.y;
     const size_t om = static_cast<size_t>(pkm) * bs;
     C x[LPT][L];
     load_codensity<T, L>(x, psi + opaque_idx(om), psi + opaque_idx(on), opaque_off(toff0));
-    fused_forward<T, L>(x, s, row0, col);
+    // warm L2 with the next partner's orbital and kernel table while the FFTs run
+    Prefetch<T> pf{nullptr, nullptr, junk};
+    if (p + 1 < p1) {
+      const int2 rn = parts[p + 1];
+      pf.orb = psi + static_cast<size_t>(rn.x * nbands + rn.y) * bs;
+      pf.tab = vtab + static_cast<size_t>(qmap[ok * nk + rn.x]) * npts;
+    }
+    fused_forward<T, L>(x, s, row0, col, pf);
     mul_kernel<T, L>(x, vtab + static_cast<size_t>(qmap[ok * nk + r.x]) * npts, opaque_off(static_cast<uint32_t>(t)));
     fused_inverse<T, L>(x, s, row0, col);
     const T coef = static_cast<T>(-kw[r.x] * occ[pkm] * f);
     const C* bm = psi + opaque_idx(om);
-    C* bo = out + opaque_idx(on);
+    C* bo = dst + opaque_idx(od);
     const uint32_t toff = opaque_off(toff0);
     // accumulate: u_m (and the running output) in double-buffered batches
     constexpr int E = LPT * L;
     constexpr int kA = 4;  // smaller batches here: x, u_m and the output are live together
     constexpr int NB = E / kA;
     C mb[2][kA], ob[2][kA];
-    const bool rmw = !Sh::ACC_REG && p > 0;
+    const bool rmw = !Sh::ACC_REG && p > p0;
 #pragma unroll
     for (int j = 0; j < kA; ++j) {
       const uint32_t a = toff + (j / L) * (Sh::RPT * LL) + (j % L) * L;
@@ -404,7 +468,7 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     }
   }
   if constexpr (Sh::ACC_REG) {
-    C* bo = out + on;
+    C* bo = dst + od;
 #pragma unroll
     for (int l = 0; l < LPT; ++l) {
       const uint32_t off = toff0 + static_cast<uint32_t>(l * Sh::RPT * LL);
@@ -484,6 +548,21 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_energy_fused(
   }
 }
 
+// out[o0 + o] += sum_s partial[s][o] (fixed order), one output per blockIdx.y
+template <typename T>
+__global__ __launch_bounds__(256) void k_add_partials(typename cx<T>::t* __restrict__ out, long long bs, int o0, int nout,
+                                                       const typename cx<T>::t* __restrict__ partial, int nparts,
+                                                       long long npts) {
+  using C = typename cx<T>::t;
+  const int o = blockIdx.y;
+  C* dst = out + static_cast<size_t>(o0 + o) * bs;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < npts; e += static_cast<long long>(gridDim.x) * 256) {
+    C v = dst[e];
+    for (int sl = 0; sl < nparts; ++sl) v = cadd(v, partial[(static_cast<size_t>(sl) * nout + o) * npts + e]);
+    dst[e] = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -497,13 +576,23 @@ hipError_t fused_apply_L(const Plan& p, const FusedGroup& g, const void* psi, co
   const Instance& in = p.inst[g.inst];
   const size_t lds = static_cast<size_t>(Sh::LDS) * sizeof(C);
   p.prof.begin(FOCK_K_FUSED, p.stream);
-  hipLaunchKernelGGL((k_pair_fused<T, L>), dim3(g.nout), dim3(Sh::NT), lds, p.stream, in.nbands,
-                     static_cast<long long>(in.band_stride), g.o0, static_cast<const C*>(psi),
-                     reinterpret_cast<const int2*>(p.ws + g.part_off), g.npart, in.nk,
+  C* partial = reinterpret_cast<C*>(p.ws + p.partial_off);
+  hipLaunchKernelGGL((k_pair_fused<T, L>), dim3(g.nout * g.nsplit), dim3(Sh::NT), lds, p.stream, in.nbands,
+                     static_cast<long long>(in.band_stride), g.o0, g.nout, static_cast<const C*>(psi),
+                     reinterpret_cast<const int2*>(p.ws + g.part_off), g.npart, g.nsplit, in.nk,
                      reinterpret_cast<const int*>(p.ws + in.qmap_off), reinterpret_cast<const T*>(p.ws + in.vtab_off),
-                     occ, reinterpret_cast<const double*>(p.ws + in.kw_off), static_cast<C*>(out), gscale, hscale,
-                     backward ? 1 : 0);
+                     occ, reinterpret_cast<const double*>(p.ws + in.kw_off), static_cast<C*>(out), partial, gscale,
+                     hscale, backward ? 1 : 0);
   p.prof.end(FOCK_K_FUSED, p.stream);
+  if (g.nsplit > 1) {
+    const size_t npts = static_cast<size_t>(in.npts);
+    const int gx = static_cast<int>(std::min<size_t>(4096, (npts + 255) / 256));
+    p.prof.begin(FOCK_K_OTHER, p.stream);
+    hipLaunchKernelGGL((k_add_partials<T>), dim3(gx, g.nout), dim3(256), 0, p.stream, static_cast<C*>(out),
+                       static_cast<long long>(in.band_stride), g.o0, g.nout, static_cast<const C*>(partial),
+                       g.nsplit - 1, static_cast<long long>(npts));
+    p.prof.end(FOCK_K_OTHER, p.stream);
+  }
   return hipGetLastError();
 }
 
@@ -570,6 +659,12 @@ bool fused_supported(fock_precision prec, const int grid[3]) {
   const int L = grid[0];
   if (prec == FOCK_C64) return L == 16 || L == 24 || L == 32;
   return L == 16;  // FP64 24^3 would spill on this path; it takes the three-pass path
+}
+
+int fused_threads(fock_precision prec, int L) {
+  if (prec == FOCK_C64) return L == 16 ? FusedShape<float, 16>::NT : L == 24 ? FusedShape<float, 24>::NT
+                                                                            : FusedShape<float, 32>::NT;
+  return FusedShape<double, 16>::NT;
 }
 
 size_t fused_lds_bytes(fock_precision prec, int L) {

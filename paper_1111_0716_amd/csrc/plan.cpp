@@ -253,6 +253,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     }
   }
   size_t max_pairs_elems = 0;  // max over batches of npairs * npts
+  size_t max_partial = 0;      // bytes of partial sums of the whole-pair path
+  const int n_cus = static_cast<int>(env_mb("FOCK_CUS", 256));
   for (const Group& g : groups) {
     const Instance& in = p->inst[g.inst];
     const int nout = (g.k1 - g.k0) * in.nbands;
@@ -265,6 +267,21 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       fg.nout = nout;
       fg.part_off = g.off;
       fg.npart = npart;
+      // partner slices: fill the resident workgroup slots evenly (fewest slices wins ties)
+      const size_t lds = fused_lds_bytes(prec, in.grid[0]);
+      const int per_cu = std::max(1, std::min<int>(static_cast<int>(160 * 1024 / lds), 2048 / fused_threads(prec, in.grid[0])));
+      const int slots = n_cus * per_cu;
+      double best = -1.0;
+      for (int sp = 1; sp <= 4 && sp <= npart; ++sp) {
+        const long long items = static_cast<long long>(nout) * sp;
+        const long long waves = (items + slots - 1) / slots;
+        const double eff = static_cast<double>(items) / static_cast<double>(waves * slots);
+        if (eff > best + 1e-9) {
+          best = eff;
+          fg.nsplit = sp;
+        }
+      }
+      max_partial = std::max(max_partial, static_cast<size_t>(fg.nsplit - 1) * nout * in.npts * p->csize);
       p->fused_groups.push_back(fg);
       p->apply_fft_pairs += static_cast<int64_t>(nout) * npart;
       continue;
@@ -346,6 +363,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->epart_off = off;
   p->epart_bytes = std::max(max_epairs * max_n2, max_fused_epairs) * sizeof(double);
   off = align_up(off + p->epart_bytes);
+  p->partial_off = off;
+  p->partial_bytes = max_partial;
+  off = align_up(off + p->partial_bytes);
   p->ebsum_off = off;
   p->ebsum_bytes = static_cast<size_t>(std::max(slot, 1)) * sizeof(double);
   off = align_up(off + p->ebsum_bytes);
@@ -355,7 +375,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     const size_t need = in.fused ? fused_lds_bytes(prec, in.grid[0]) + 256 : std::max(plane, tile) * p->csize + 64;
     p->lds_needed = std::max(p->lds_needed, need);
   }
-  p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size()) + static_cast<int64_t>(p->fused_groups.size());
+  p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size());
+  for (const FusedGroup& g : p->fused_groups) p->apply_launches += g.nsplit > 1 ? 2 : 1;
 
   // ---- host image of the constant prefix ----
   p->host_image.assign(p->const_bytes, 0);
