@@ -151,6 +151,14 @@ typedef enum {
 fock_status fock_profile_enable(fock_plan_t plan, int enable);
 fock_status fock_profile_read(fock_plan_t plan, int kind, double* total_ms, int64_t* launches);
 
+/* Graph replay: when enabled, each of fock_apply, fock_energy and
+ * fock_energy_backward records its whole launch sequence (every instance,
+ * every batch) into one HIP graph on first use and replays it with a single
+ * graph launch while the argument pointers stay the same (a new pointer set
+ * records a new graph).  Needs a plan stream other than the legacy default
+ * stream (FOCK_ERR_STATE otherwise).  Results are identical to eager launches. */
+fock_status fock_set_graph(fock_plan_t plan, int enable);
+
 /* Release the plan (host memory; the caller frees the workspace). NULL is a no-op. */
 fock_status fock_destroy(fock_plan_t plan);
 

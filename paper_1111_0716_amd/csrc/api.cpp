@@ -1,6 +1,8 @@
 // C ABI of libfock.so (declared in include/fock.h).
 #include <cmath>
 #include <cstdint>
+#include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 
@@ -114,6 +116,52 @@ fock_status run_apply(Plan* p, const void* const* psi, const double* const* occ,
   return FOCK_OK;
 }
 
+// Run `enqueue` eagerly, or replay (recording first if needed) the graph of
+// its launches for this argument set.
+template <typename F>
+fock_status with_graph(Plan* p, GraphCache& cache, std::vector<uintptr_t> key, F&& enqueue) {
+  if (!p->use_graph) return enqueue();
+  if (cache.exec && cache.key == key) {
+    const hipError_t e = hipGraphLaunch(cache.exec, p->stream);
+    return e == hipSuccess ? FOCK_OK : hip_fail(e, "graph launch");
+  }
+  cache.release();
+  const bool prof_on = p->prof.on;
+  p->prof.on = false;  // no event nodes in the graph
+  hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    p->prof.on = prof_on;
+    return hip_fail(e, "begin capture");
+  }
+  const fock_status st = enqueue();
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(p->stream, &graph);
+  p->prof.on = prof_on;
+  if (st != FOCK_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  e = hipGraphInstantiate(&cache.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    cache.exec = nullptr;
+    return hip_fail(e, "graph instantiate");
+  }
+  cache.key = std::move(key);
+  e = hipGraphLaunch(cache.exec, p->stream);
+  return e == hipSuccess ? FOCK_OK : hip_fail(e, "graph launch");
+}
+
+std::vector<uintptr_t> ptr_key(const Plan* p, std::initializer_list<const void* const*> arrays,
+                               std::initializer_list<uintptr_t> extra) {
+  std::vector<uintptr_t> k;
+  for (const void* const* a : arrays)
+    for (size_t i = 0; i < p->inst.size(); ++i) k.push_back(a ? reinterpret_cast<uintptr_t>(a[i]) : 0);
+  for (uintptr_t x : extra) k.push_back(x);
+  return k;
+}
+
 }  // namespace
 }  // namespace fock
 
@@ -186,7 +234,14 @@ fock_status fock_set_workspace(fock_plan_t plan, void* dev_ptr, size_t bytes) {
 fock_status fock_set_stream(fock_plan_t plan, void* hip_stream) {
   clear_error();
   if (!plan) return set_error(FOCK_ERR_ARG, "plan is NULL");
-  reinterpret_cast<Plan*>(plan)->stream = static_cast<hipStream_t>(hip_stream);
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  if (p->use_graph && p->stream == nullptr) {
+    p->use_graph = false;
+    p->g_apply.release();
+    p->g_energy.release();
+    p->g_backward.release();
+  }
   return FOCK_OK;
 }
 
@@ -201,16 +256,23 @@ fock_status fock_apply(fock_plan_t plan, const void* const* psi, const double* c
   if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
   for (size_t i = 0; i < p->inst.size(); ++i)
     if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
-  s = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false);
-  if (s != FOCK_OK) return s;
-  if (vmat) {
-    for (size_t i = 0; i < p->inst.size(); ++i) {
-      if (!vmat[i]) continue;
-      const hipError_t e = launch_overlap(*p, static_cast<int>(i), psi[i], vx_psi[i], vmat[i]);
-      if (e != hipSuccess) return hip_fail(e, "overlap launch");
+  auto enqueue = [&]() -> fock_status {
+    fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false);
+    if (st != FOCK_OK) return st;
+    if (vmat) {
+      for (size_t i = 0; i < p->inst.size(); ++i) {
+        if (!vmat[i]) continue;
+        const hipError_t e = launch_overlap(*p, static_cast<int>(i), psi[i], vx_psi[i], vmat[i]);
+        if (e != hipSuccess) return hip_fail(e, "overlap launch");
+      }
     }
-  }
-  return FOCK_OK;
+    return FOCK_OK;
+  };
+  return with_graph(p, p->g_apply,
+                    ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
+                                reinterpret_cast<const void* const*>(vmat)},
+                            {reinterpret_cast<uintptr_t>(vmat)}),
+                    enqueue);
 }
 
 fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* const* occ, double* ex) {
@@ -221,21 +283,26 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
   if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
   if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
   if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
-  for (const Batch& b : p->energy_batches) {
-    hipError_t e;
-    if (p->inst[b.inst].fused) {
-      e = launch_fused_energy(*p, b, psi[b.inst]);
-      if (e == hipSuccess) e = launch_energy_reduce(*p, b, occ[b.inst], 1);
-    } else {
-      e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
+  auto enqueue = [&]() -> fock_status {
+    for (const Batch& b : p->energy_batches) {
+      hipError_t e;
+      if (p->inst[b.inst].fused) {
+        e = launch_fused_energy(*p, b, psi[b.inst]);
+        if (e == hipSuccess) e = launch_energy_reduce(*p, b, occ[b.inst], 1);
+      } else {
+        e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
+      }
+      if (e != hipSuccess) return hip_fail(e, "energy batch launch");
     }
-    if (e != hipSuccess) return hip_fail(e, "energy batch launch");
-  }
-  for (size_t i = 0; i < p->inst.size(); ++i) {
-    const hipError_t e = launch_energy_finish(*p, static_cast<int>(i), ex + i);
-    if (e != hipSuccess) return hip_fail(e, "energy finish launch");
-  }
-  return FOCK_OK;
+    for (size_t i = 0; i < p->inst.size(); ++i) {
+      const hipError_t e = launch_energy_finish(*p, static_cast<int>(i), ex + i);
+      if (e != hipSuccess) return hip_fail(e, "energy finish launch");
+    }
+    return FOCK_OK;
+  };
+  return with_graph(p, p->g_energy, ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ)},
+                                            {reinterpret_cast<uintptr_t>(ex)}),
+                    enqueue);
 }
 
 fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const double* const* occ,
@@ -251,7 +318,28 @@ fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const
   if (!std::isfinite(scale)) return set_error(FOCK_ERR_ARG, "scale not finite");
   for (size_t i = 0; i < p->inst.size(); ++i)
     if (grad_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "grad_psi aliases psi");
-  return run_apply(p, psi, occ, grad_psi, grad_ex, scale, true);
+  uint64_t sbits;
+  static_assert(sizeof(sbits) == sizeof(scale), "double is 64-bit");
+  std::memcpy(&sbits, &scale, sizeof(sbits));
+  return with_graph(p, p->g_backward,
+                    ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(grad_psi)},
+                            {reinterpret_cast<uintptr_t>(grad_ex), static_cast<uintptr_t>(sbits)}),
+                    [&]() { return run_apply(p, psi, occ, grad_psi, grad_ex, scale, true); });
+}
+
+fock_status fock_set_graph(fock_plan_t plan, int enable) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  if (enable && p->stream == nullptr)
+    return set_error(FOCK_ERR_STATE, "graph replay needs a stream other than the legacy default stream");
+  p->use_graph = enable != 0;
+  if (!p->use_graph) {
+    p->g_apply.release();
+    p->g_energy.release();
+    p->g_backward.release();
+  }
+  return FOCK_OK;
 }
 
 fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* apply_fft_pairs,

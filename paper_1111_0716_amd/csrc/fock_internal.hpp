@@ -78,6 +78,17 @@ struct Profiler {
   void release();
 };
 
+// A captured launch sequence and the arguments it was captured with.
+struct GraphCache {
+  std::vector<uintptr_t> key;
+  hipGraphExec_t exec = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key.clear();
+  }
+};
+
 struct Plan {
   fock_precision prec;
   size_t csize;  // sizeof(complex element)
@@ -92,6 +103,7 @@ struct Plan {
   size_t epart_off = 0, epart_bytes = 0;
   size_t ebsum_off = 0, ebsum_bytes = 0;
   size_t partial_off = 0, partial_bytes = 0;
+  size_t ovl_off = 0, ovl_bytes = 0;  // overlap split-K partials
   size_t total_bytes = 0;
   std::vector<unsigned char> host_image;  // constant prefix, uploaded by set_workspace
   unsigned char* ws = nullptr;            // device workspace (caller-owned)
@@ -102,7 +114,14 @@ struct Plan {
   size_t max_lds = 0;      // per-block LDS limit of the device
   size_t lds_needed = 0;   // largest dynamic LDS of any launch (+ static)
   mutable Profiler prof;
-  ~Plan() { prof.release(); }
+  bool use_graph = false;
+  GraphCache g_apply, g_energy, g_backward;
+  ~Plan() {
+    prof.release();
+    g_apply.release();
+    g_energy.release();
+    g_backward.release();
+  }
 };
 
 // status helpers (thread-local last error)
@@ -121,6 +140,7 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
 bool fused_supported(fock_precision prec, const int grid[3]);
 size_t fused_lds_bytes(fock_precision prec, int L);
 int fused_threads(fock_precision prec, int L);
+size_t overlap_scratch_bytes(const Instance& in);
 void prepare_fused_kernels(fock_precision prec, int lim);
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
                               const double* gscale, double hscale, bool backward);

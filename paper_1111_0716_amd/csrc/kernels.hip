@@ -259,31 +259,6 @@ __global__ void k_energy_finish(const double* __restrict__ ebsum, int first, int
 }
 
 // ---------------------------------------------------------------------------
-// band overlap M[k][i][j] = dV sum conj(u_ki) (V_x u)_kj  (FP64 accumulation)
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_overlap(const typename cx<T>::t* __restrict__ psi,
-                                                    const typename cx<T>::t* __restrict__ vx, int nbands,
-                                                    long long bs, long long npts, double dv,
-                                                    typename cx<T>::t* __restrict__ vmat) {
-  using C = typename cx<T>::t;
-  __shared__ double red[kBlock / 64];
-  const int ij = blockIdx.x, k = blockIdx.y;
-  const int i = ij / nbands, j = ij - i * nbands;
-  const C* a = psi + static_cast<size_t>(k * nbands + i) * bs;
-  const C* b = vx + static_cast<size_t>(k * nbands + j) * bs;
-  double re = 0.0, im = 0.0;
-  for (long long e = threadIdx.x; e < npts; e += kBlock) {
-    const double ax = a[e].x, ay = a[e].y, bx = b[e].x, by = b[e].y;
-    re += ax * bx + ay * by;
-    im += ax * by - ay * bx;
-  }
-  const double tr = block_sum(re, red);
-  const double ti = block_sum(im, red);
-  if (threadIdx.x == 0) vmat[(static_cast<size_t>(k) * nbands + i) * nbands + j] = C{T(tr * dv), T(ti * dv)};
-}
-
-// ---------------------------------------------------------------------------
 // zero the outputs of k-points that have no partner in the k-pair list
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -360,18 +335,6 @@ hipError_t energy_batch_t(const Plan& p, const Batch& b, const void* psi, const 
   return launch_energy_reduce(p, b, occ, g.n2);
 }
 
-template <typename T>
-hipError_t overlap_t(const Plan& p, int inst, const void* psi, const void* vx, void* vmat) {
-  using C = typename cx<T>::t;
-  const Instance& in = p.inst[inst];
-  p.prof.begin(FOCK_K_OVERLAP, p.stream);
-  hipLaunchKernelGGL((k_overlap<T>), dim3(in.nbands * in.nbands, in.nk), dim3(kBlock), 0, p.stream,
-                     static_cast<const C*>(psi), static_cast<const C*>(vx), in.nbands,
-                     static_cast<long long>(in.band_stride), static_cast<long long>(in.npts),
-                     in.omega / static_cast<double>(in.npts), static_cast<C*>(vmat));
-  p.prof.end(FOCK_K_OVERLAP, p.stream);
-  return hipGetLastError();
-}
 
 // Dynamic LDS above 64 KiB: ask for the device's per-block limit.  The call
 // is advisory on ROCm (launches beyond 64 KiB succeed up to the hardware
@@ -460,8 +423,5 @@ hipError_t launch_energy_finish(const Plan& p, int inst, double* ex) {
   return hipGetLastError();
 }
 
-hipError_t launch_overlap(const Plan& p, int inst, const void* psi, const void* vx, void* vmat) {
-  return p.prec == FOCK_C128 ? overlap_t<double>(p, inst, psi, vx, vmat) : overlap_t<float>(p, inst, psi, vx, vmat);
-}
 
 }  // namespace fock

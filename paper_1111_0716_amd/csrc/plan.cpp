@@ -366,6 +366,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->partial_off = off;
   p->partial_bytes = max_partial;
   off = align_up(off + p->partial_bytes);
+  p->ovl_off = off;
+  for (const auto& in : p->inst) p->ovl_bytes = std::max(p->ovl_bytes, overlap_scratch_bytes(in));
+  off = align_up(off + p->ovl_bytes);
   p->ebsum_off = off;
   p->ebsum_bytes = static_cast<size_t>(std::max(slot, 1)) * sizeof(double);
   off = align_up(off + p->ebsum_bytes);

@@ -22,7 +22,7 @@ FOCK_C128, FOCK_C64 = 0, 1
 
 EXPORTED = ["fock_plan", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
             "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_profile_enable", "fock_profile_read",
-            "fock_destroy", "fock_status_string", "fock_last_error"]
+            "fock_set_graph", "fock_destroy", "fock_status_string", "fock_last_error"]
 KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
                 "other", "fused", "energy_fused"]
 
@@ -70,6 +70,7 @@ def lib():
                                       POINTER(c_int64)]
         L.fock_profile_enable.argtypes = [c_void_p, c_int]
         L.fock_profile_read.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(c_int64)]
+        L.fock_set_graph.argtypes = [c_void_p, c_int]
         L.fock_destroy.argtypes = [c_void_p]
         L.fock_status_string.argtypes = [c_int]
         L.fock_status_string.restype = c_char_p
@@ -232,6 +233,12 @@ class Plan:
         a, b, c, d = c_int64(), c_int64(), c_int64(), c_int64()
         check(lib().fock_plan_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
         return dict(ordered_pairs=a.value, apply_fft_pairs=b.value, energy_fft_pairs=c.value, apply_launches=d.value)
+
+    def set_graph(self, enable=True):
+        """Record each call's launch sequence into one HIP graph and replay it
+        (needs a non-default stream: pass ``stream=torch.cuda.Stream()``)."""
+        self._sync_stream()
+        check(lib().fock_set_graph(self.handle, 1 if enable else 0))
 
     def profile(self, enable=True):
         """Bracket every library launch with HIP events on the plan stream."""
