@@ -184,6 +184,72 @@ def cpu_baseline(inst, seconds):
                 kind="oracle", sample=f"{npairs} ordered pairs (outputs k=0, n<= {n}; every k', m) in {el:.1f} s")
 
 
+def ragged(args):
+    """Uneven batch: 48 independent instances (grids 24^3-64^3, 8-96 bands,
+    Gamma or 2x2x2) in one plan with autotuned schedule knobs, replayed as one
+    HIP graph per call (FP32), beside one-at-a-time FP64 plans."""
+    import torch
+
+    from paper_1111_0716_amd import autotune, fock, inputs
+
+    device = torch.device("cuda:0")
+    log("generating the 48-instance uneven batch")
+    insts = inputs.uneven_batch(dtype=np.complex128, workers=16)
+    pairs = sum(i.ordered_pairs() for i in insts)
+    stream = torch.cuda.Stream(device)
+    with torch.cuda.stream(stream):
+        psi = [torch.from_numpy(i.psi.astype(np.complex64)).to(device) for i in insts]
+        occ = [torch.from_numpy(i.occ).to(device) for i in insts]
+        tuning, rec = autotune.autotune(insts, psi, occ, precision="c64", device=device, log=log)
+        plan = fock.Plan(insts, precision="c64", device=device, stream=stream, tuning=tuning)
+        plan.set_graph(True)
+        out = [torch.empty_like(p) for p in psi]
+        ex = torch.empty(len(insts), dtype=torch.float64, device=device)
+
+        def step():
+            plan.fock_apply(psi, occ, out=out)
+            plan.fock_energy(psi, occ, ex=ex)
+
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        plan.close()
+        del psi, out
+        torch.cuda.empty_cache()
+    log("one-at-a-time FP64 plans")
+    ms64 = 0.0
+    for inst in insts:
+        p64 = fock.Plan([inst], precision="c128", device=device)
+        ps = torch.from_numpy(inst.psi).to(device)
+        oc = torch.from_numpy(inst.occ).to(device)
+        o = torch.empty_like(ps)
+        p64.fock_apply([ps], [oc], out=[o])
+        p64.fock_energy([ps], [oc])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p64.fock_apply([ps], [oc], out=[o])
+        p64.fock_energy([ps], [oc])
+        torch.cuda.synchronize()
+        ms64 += (time.perf_counter() - t0) * 1e3
+        p64.close()
+        del ps, o
+    line = {"metric": "band-pair Fock applications/s, uneven batch (48 instances), FP32 one graph vs FP64 one-at-a-time",
+            "value": round(pairs / (ms / 1e3), 1), "unit": "ordered band pairs/s (apply + energy per step)",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 complex)",
+            "data": "synthetic", "config": {"workload": "48 uneven instances", "ordered_pairs_per_step": pairs,
+                                            "tuning": tuning},
+            "fp64_one_at_a_time": {"ms_per_step": round(ms64, 3), "pairs_per_s": round(pairs / (ms64 / 1e3), 1)}}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,11 +259,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", choices=["alpha", "ragged"], default="alpha")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               f"(the exchange path of this library runs on a single device).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "ragged":
+        return ragged(args)
 
     import torch
 

@@ -88,6 +88,25 @@ typedef struct {
 fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
                       fock_plan_t* out);
 
+/* Schedule knobs (0 = library default).  Chosen by measurement with the
+ * autotuner (paper_1111_0716_amd/autotune.py) or left at the defaults.
+ *   acc_workgroups  three-pass path: target workgroups of the accumulate pass,
+ *                   which sets the output block |O| = ceil(target / N1)
+ *   tbuf_mb         three-pass path: pair-buffer budget (MiB), which bounds
+ *                   |O| x |P| pairs per batch
+ *   fused_split     whole-pair path: partner slices per output (1..4)
+ *   no_fused        1: use the three-pass path for every grid */
+typedef struct {
+  int32_t acc_workgroups;
+  int32_t tbuf_mb;
+  int32_t fused_split;
+  int32_t no_fused;
+} fock_tuning;
+
+/* fock_plan with explicit schedule knobs (tuning may be NULL = defaults). */
+fock_status fock_plan_tuned(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
+                            const fock_tuning* tuning, fock_plan_t* out);
+
 /* Bytes of device workspace the plan needs (tables, schedule, scratch). */
 fock_status fock_workspace_size(fock_plan_t plan, size_t* bytes);
 

@@ -22,7 +22,8 @@ fock_status set_error(fock_status s, const std::string& msg) {
 void clear_error() { g_last_error.clear(); }
 
 fock_status validate_desc(const fock_desc& d, int idx);
-fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, Plan** out);
+fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, const fock_tuning* tune,
+                       Plan** out);
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
 
 hipEvent_t Profiler::next(hipStream_t s) {
@@ -171,6 +172,11 @@ extern "C" {
 
 fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
                       fock_plan_t* out) {
+  return fock_plan_tuned(descs, n_inst, prec, hip_stream, nullptr, out);
+}
+
+fock_status fock_plan_tuned(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
+                            const fock_tuning* tuning, fock_plan_t* out) {
   clear_error();
   if (!out) return set_error(FOCK_ERR_ARG, "out is NULL");
   if (!descs) return set_error(FOCK_ERR_ARG, "descs is NULL");
@@ -182,7 +188,10 @@ fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision pre
   }
   try {
     Plan* p = nullptr;
-    const fock_status s = build_plan(descs, n_inst, prec, hip_stream, &p);
+    if (tuning && (tuning->acc_workgroups < 0 || tuning->tbuf_mb < 0 || tuning->fused_split < 0 ||
+                   tuning->fused_split > 4))
+      return set_error(FOCK_ERR_ARG, "tuning knob out of range");
+    const fock_status s = build_plan(descs, n_inst, prec, hip_stream, tuning, &p);
     if (s != FOCK_OK) return s;
     *out = reinterpret_cast<fock_plan_t>(p);
     return FOCK_OK;

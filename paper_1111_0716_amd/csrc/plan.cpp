@@ -145,7 +145,9 @@ fock_status validate_desc(const fock_desc& d, int idx) {
   return FOCK_OK;
 }
 
-fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, Plan** out) {
+fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, const fock_tuning* tune,
+                       Plan** out) {
+  const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0};
   auto p = std::make_unique<Plan>();
   p->prec = prec;
   p->csize = prec == FOCK_C128 ? 16 : 8;
@@ -210,10 +212,12 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     in.nq = static_cast<int>(qidx.size());
   }
   const char* nofused = std::getenv("FOCK_NO_FUSED");
-  for (auto& in : p->inst) in.fused = fused_supported(prec, in.grid) && !(nofused && *nofused && *nofused != '0');
+  const bool no_fused = tn.no_fused != 0 || (nofused && *nofused && *nofused != '0');
+  for (auto& in : p->inst) in.fused = fused_supported(prec, in.grid) && !no_fused;
 
   // ---- batch shapes ----
-  const size_t tbuf_target = env_mb("FOCK_TBUF_MB", 1024) << 20;
+  const size_t tbuf_target = (tn.tbuf_mb > 0 ? static_cast<size_t>(tn.tbuf_mb) : env_mb("FOCK_TBUF_MB", 1024)) << 20;
+  const int acc_wgs = tn.acc_workgroups > 0 ? tn.acc_workgroups : 2048;
 
   // ---- workspace layout: constant prefix ----
   size_t off = 0;
@@ -273,6 +277,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       const int slots = n_cus * per_cu;
       double best = -1.0;
       for (int sp = 1; sp <= 4 && sp <= npart; ++sp) {
+        if (tn.fused_split > 0 && sp != std::min(tn.fused_split, npart)) continue;
         const long long items = static_cast<long long>(nout) * sp;
         const long long waves = (items + slots - 1) / slots;
         const double eff = static_cast<double>(items) / static_cast<double>(waves * slots);
@@ -288,7 +293,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     }
     const size_t pair_bytes = static_cast<size_t>(in.npts) * p->csize;
     const int pmax = static_cast<int>(std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes)));
-    int nO = std::max(1, std::min(nout, (2048 + in.grid[0] - 1) / in.grid[0]));
+    int nO = std::max(1, std::min(nout, (acc_wgs + in.grid[0] - 1) / in.grid[0]));
     nO = std::min(nO, pmax);
     const int nP = std::max(1, std::min(npart, pmax / nO));
     for (int ob = 0; ob < nout; ob += nO) {

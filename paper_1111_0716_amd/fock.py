@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libfock.so")
 FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FOCK_ERR_STATE = range(6)
 FOCK_C128, FOCK_C64 = 0, 1
 
-EXPORTED = ["fock_plan", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
+EXPORTED = ["fock_plan", "fock_plan_tuned", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
             "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_profile_enable", "fock_profile_read",
             "fock_set_graph", "fock_destroy", "fock_status_string", "fock_last_error"]
 KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
@@ -31,6 +31,10 @@ class FockError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{msg} (status {status})")
         self.status = status
+
+
+class FockTuning(ctypes.Structure):
+    _fields_ = [("acc_workgroups", c_int32), ("tbuf_mb", c_int32), ("fused_split", c_int32), ("no_fused", c_int32)]
 
 
 class FockDesc(ctypes.Structure):
@@ -59,6 +63,8 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)
         L.fock_plan.argtypes = [POINTER(FockDesc), c_int32, c_int, c_void_p, POINTER(c_void_p)]
+        L.fock_plan_tuned.argtypes = [POINTER(FockDesc), c_int32, c_int, c_void_p, POINTER(FockTuning),
+                                      POINTER(c_void_p)]
         L.fock_workspace_size.argtypes = [c_void_p, POINTER(c_size_t)]
         L.fock_set_workspace.argtypes = [c_void_p, c_void_p, c_size_t]
         L.fock_set_stream.argtypes = [c_void_p, c_void_p]
@@ -133,7 +139,7 @@ class Plan:
     (e.g. paper_1111_0716_amd.inputs.Instance) or dicts with those keys.
     ``precision``: "c64" (FP32 path) or "c128" (FP64 path)."""
 
-    def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None):
+    def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None, tuning=None):
         import torch
 
         self.torch = torch
@@ -157,7 +163,10 @@ class Plan:
             n = int(np.prod(g))
             self.meta.append(dict(nk=descs[i].nk, nbands=nb, npts=n, omega=abs(float(np.linalg.det(lat)))))
         handle = c_void_p()
-        check(lib().fock_plan(descs, len(instances), self.prec, c_void_p(self._stream_ptr()), ctypes.byref(handle)))
+        self.tuning = dict(tuning) if tuning else {}
+        tn = FockTuning(**{k: int(v) for k, v in self.tuning.items()}) if tuning else None
+        check(lib().fock_plan_tuned(descs, len(instances), self.prec, c_void_p(self._stream_ptr()),
+                                    ctypes.byref(tn) if tn is not None else None, ctypes.byref(handle)))
         self.handle = handle
         size = c_size_t()
         check(lib().fock_workspace_size(self.handle, ctypes.byref(size)))

@@ -221,3 +221,28 @@ def test_ragged_batch_one_graph_against_single_fp64(device):
         vref, eref = o.apply(inst.psi.astype(np.complex64).astype(np.complex128), inst.occ)
         assert band_err(vx32[i].astype(np.complex128), vref) <= 1e-5
         assert abs(ex32[i] - eref) <= 1e-6 * abs(eref)
+
+
+def test_autotuner_picks_a_valid_schedule(device, tmp_path, monkeypatch):
+    """The autotuner times candidate schedules on the device and the tuned
+    plan computes the same operator (to FP64 rounding)."""
+    import torch
+
+    from paper_1111_0716_amd import autotune, fock
+
+    monkeypatch.setenv("FOCK_TUNE_CACHE", str(tmp_path / "tune.json"))
+    insts = [inputs.small_instance(grid=(24, 20, 18), kmesh=(2, 1, 1), nbands=5, seed=(301, 0)),
+             inputs.small_instance(grid=(16, 16, 16), kmesh=(1, 1, 1), nbands=4, seed=(301, 1))]
+    psi = [to_dev(i.psi, device) for i in insts]
+    occ = [to_dev(i.occ, device) for i in insts]
+    tuning, rec = autotune.autotune(insts, psi, occ, precision="c128", device=device, log=log)
+    assert len(rec["trials"]) >= 4
+    tuning2, rec2 = autotune.autotune(insts, psi, occ, precision="c128", device=device)
+    assert tuning2 == tuning  # from the cache
+    p0 = fock.Plan(insts, precision="c128", device=device)
+    p1 = fock.Plan(insts, precision="c128", device=device, tuning=tuning)
+    v0, _ = p0.fock_apply(psi, occ)
+    v1, _ = p1.fock_apply(psi, occ)
+    torch.cuda.synchronize()
+    for a, b in zip(v0, v1):
+        assert band_err(b.cpu().numpy(), a.cpu().numpy()) <= 1e-12
