@@ -31,6 +31,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# copy-calibrated HBM traffic of the dominant FP32 kernel, written by
+# paper_1111_0716_amd.profile_summary from rocprofv3 counter runs of this script
+TRAFFIC_FILES = {"alpha": "profiles/{kind}_alpha_boron_32cubed_fp32_traffic.md"}
+WORKLOADS = {
+    "2": "alpha-boron-shaped rhombohedral cell a=9.56 bohr alpha=58.0 deg, 32^3 grid, 4x4x4 k-mesh "
+         "(all 64 k' per k), 18 bands f=1, mu=0.106",
+    "3": "beta-boron-shaped rhombohedral cell a=19.16 bohr alpha=65.2 deg, 72^3 grid, 2x2x2 k-mesh, "
+         "160 bands (8 fractional), mu=0.106",
+    "5": "beta-boron-shaped cell a=19.16 bohr alpha=65.2 deg, 64^3 grid, Gamma, 128 bands, mu=0.106",
+}
 # Vector ALU peak without packed FP32 math: 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz.
 VALU_PEAK_TFLOPS = {"c64": 78.6, "c128": 78.6}
 
@@ -68,7 +78,7 @@ def kernel_model(grid, s):
     }
 
 
-def roofline(kern, stats, grid, s, peak_tflops):
+def roofline(kern, stats, grid, s, peak_tflops, traffic_file=None):
     """Roofline entry of the kernel kind with the largest share of the
     profiled step (apply, energy and backward: apply kinds run twice)."""
     model = kernel_model(grid, s)
@@ -90,7 +100,12 @@ def roofline(kern, stats, grid, s, peak_tflops):
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
-    roof.update({"traffic": None, "kernel": dom, "launches": launches, "launch_ms": round(per_launch_ms, 4),
+    traffic = None
+    if traffic_file:
+        from paper_1111_0716_amd.profile_summary import read_traffic
+        traffic = read_traffic(os.path.join(ROOT, traffic_file.format(kind=dom)), dom)
+    roof.update({"traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                 "copy-calibrated)", "algorithmic_bytes_per_launch": byts, "kernel": dom, "launches": launches, "launch_ms": round(per_launch_ms, 4),
                  "units_per_launch": round(units[dom] / launches, 1),
                  "alt": {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "alu_tflops": round(tflops, 3),
                          "alu_frac": round(alu_frac, 4)}})
@@ -119,29 +134,36 @@ def run_path(inst, prec, steps, warmup, device, profile=True):
         plan.fock_energy_backward([psi], [occ], gex, scale, out=[grad])
         return ex
 
-    for _ in range(warmup):
+    for i in range(warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log(f"  warm-up step {i + 1}/{warmup} done")
     stream = torch.cuda.current_stream(device)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # the library's per-kernel HIP events stay on through the timed steps:
+    # they are recorded on the stream the kernels run on
+    plan.profile_read()
+    plan.profile(profile)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
+    for i in range(steps):
         ex = step()
+        if steps > 1:
+            # one host sync per step keeps progress visible; it adds only a
+            # launch latency between steps
+            torch.cuda.synchronize()
+            log(f"  timed step {i + 1}/{steps} done")
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
     res = dict(ms_per_step=ms, wall_s=wall, stats=st, ex=float(ex.item()))
     if profile:
-        plan.profile(True)
-        step()
-        torch.cuda.synchronize()
-        res["kernels"] = plan.profile_read()
+        res["kernels"] = {k: (v[0] / steps, v[1] // steps) for k, v in plan.profile_read().items()}
         plan.profile(False)
         # apply-only timing (one call) for the breakdown
-        t = plan.profile_read()  # reset
+        plan.profile_read()  # reset
         plan.profile(True)
         plan.fock_apply([psi], [occ], out=[out], vmat=False)
         torch.cuda.synchronize()
@@ -259,7 +281,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=["alpha", "ragged"], default="alpha")
+    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged"], default="alpha")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (the reference dispatch "
+                         "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -274,9 +299,19 @@ def main():
     from paper_1111_0716_amd import inputs
 
     device = torch.device("cuda:0")
-    log("generating inputs: alpha-boron-shaped 32^3, 4x4x4 k-mesh, 18 bands")
-    inst = inputs.config("2", dtype=np.complex128, workers=8)
+    cfg = {"alpha": "2", "beta": "3", "diff": "5"}[args.workload]
+    log(f"generating inputs: preset {cfg} ({WORKLOADS[cfg]})")
+    inst = inputs.config(cfg, dtype=np.complex128, workers=16)
     inst32 = inst.astype(np.complex64)
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device=device)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {nbytes} bytes device to device")
+        del src, dst
+        torch.cuda.empty_cache()
 
     log(f"FP32 path: {args.warmup} warm-up + {args.steps} timed steps")
     r32 = run_path(inst32, "c64", args.steps, args.warmup, device)
@@ -291,7 +326,8 @@ def main():
     pairs = r32["stats"]["ordered_pairs"]
     value = pairs / (r32["ms_per_step"] / 1e3)
 
-    roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"])
+    roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
+                    traffic_file=TRAFFIC_FILES.get(args.workload))
 
     line = {
         "metric": "band-pair Fock applications/s, FP32 vs FP64 path, + % of HBM roofline",
@@ -306,8 +342,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 (fp32 complex)",
         "data": "synthetic (seeded random orthonormal orbitals, 12 Ha cutoff)",
-        "config": {"workload": "alpha-boron-shaped rhombohedral cell a=9.56 bohr alpha=58.0 deg, 32^3 grid, "
-                               "4x4x4 k-mesh (all 64 k' per k), 18 bands f=1, mu=0.106",
+        "config": {"workload": WORKLOADS[cfg],
                    "ordered_pairs_per_step": pairs, "grid": list(inst.grid), "nk": inst.nk, "nbands": inst.nbands},
         "roofline": roof,
         "fp32": {"ms_per_step": round(r32["ms_per_step"], 3), "pairs_per_s": round(value, 1),

@@ -103,16 +103,6 @@ struct FusedShape {
   static constexpr int LDS = XA > XB ? XA : XB;
   // accumulate V_x u in registers when it fits beside the lines
   static constexpr bool ACC_REG = (L <= 16) || (L <= 24 && sizeof(T) == 4);
-  // LDS staging of orbital operands: quarters of the j2 axis (QL planes each),
-  // two orbitals per quarter, copied by 16-byte LDS-DMA loads
-  static constexpr int SZ = static_cast<int>(sizeof(C));
-  static constexpr int NQ = (2 * L * L * L * SZ <= LDS * SZ) ? 1 : (L * L * L * SZ <= LDS * SZ) ? 2 : 4;
-  static constexpr int QL = L / NQ;
-  static constexpr int RUN = QL * L * SZ;      // bytes of one j1 run of a quarter
-  static constexpr int QBYTES = L * RUN;       // bytes of one orbital quarter
-  static constexpr int CPT = QBYTES / 16 / NT; // 16-byte chunks per thread
-  static_assert(L % NQ == 0 && RUN % 16 == 0 && (QBYTES / 16) % NT == 0, "staging shape");
-  static_assert(2 * QBYTES <= LDS * SZ, "two staged quarters must fit the exchange buffer");
   // 128-byte lines of one orbital and of one table, and their share per thread
   static constexpr int ORB_LINES = (L * L * L * static_cast<int>(sizeof(C))) / 128;
   static constexpr int TAB_LINES = (L * L * L * static_cast<int>(sizeof(T))) / 128;
@@ -138,18 +128,17 @@ struct Prefetch {
 template <typename T, int L>
 __device__ __forceinline__ void prefetch_lines(const typename cx<T>::t* orb, const T* tab, int t, float* junk) {
   using Sh = FusedShape<T, L>;
-  const unsigned char* o = reinterpret_cast<const unsigned char*>(orb);
-  const unsigned char* b = reinterpret_cast<const unsigned char*>(tab);
-  const uint32_t toff = opaque_off(static_cast<uint32_t>(t) * 128u);
+  const float* o = reinterpret_cast<const float*>(orb);
+  const float* b = reinterpret_cast<const float*>(tab);
 #pragma unroll
   for (int k = 0; k < Sh::PF_ORB; ++k) {
-    if (t + k * Sh::NT < Sh::ORB_LINES)
-      __builtin_amdgcn_global_load_lds((gptr_t)(o + toff + k * Sh::NT * 128u), (lptr_t)junk, 4, 0, 0);
+    const int line = t + k * Sh::NT;
+    if (line < Sh::ORB_LINES) __builtin_amdgcn_global_load_lds((gptr_t)(o + line * 32), (lptr_t)junk, 4, 0, 0);
   }
 #pragma unroll
   for (int k = 0; k < Sh::PF_TAB; ++k) {
-    if (t + k * Sh::NT < Sh::TAB_LINES)
-      __builtin_amdgcn_global_load_lds((gptr_t)(b + toff + k * Sh::NT * 128u), (lptr_t)junk, 4, 0, 0);
+    const int line = t + k * Sh::NT;
+    if (line < Sh::TAB_LINES) __builtin_amdgcn_global_load_lds((gptr_t)(b + line * 32), (lptr_t)junk, 4, 0, 0);
   }
 }
 
@@ -173,33 +162,6 @@ struct StridedRun {
     return i < H ? lds_at<C>(s, b0 + i * STRIDE) : lds_at<C>(s, b1 + (i - H) * STRIDE);
   }
 };
-
-// Copy quarter q (j2 in [q QL, (q+1) QL)) of one orbital into LDS at byte
-// offset `dst` as L runs of RUN bytes (run j1 at dst + j1 RUN).  Each lane
-// moves 16-byte chunks straight into LDS (no registers); a wave's lanes land
-// contiguously, so chunk u sits at dst + 16 u.  `aux` = cache-policy bits.
-template <typename T, int L, int AUX>
-__device__ __forceinline__ void stage_quarter(const typename cx<T>::t* orb, int q, unsigned char* lds, uint32_t dst) {
-  using Sh = FusedShape<T, L>;
-  constexpr int CPR = Sh::RUN / 16;  // chunks per run
-  static_assert(Sh::NT % CPR == 0, "a thread's chunks must sit in whole runs");
-  // chunk u = k NT + t lies in run k (NT/CPR) + t/CPR at byte (t % CPR) 16: the
-  // per-thread part is one 32-bit offset, the per-k part a constant
-  const int t = threadIdx.x, w = t >> 6;
-  const unsigned char* g = reinterpret_cast<const unsigned char*>(orb) + static_cast<size_t>(q) * Sh::QL * L * Sh::SZ;
-  const uint32_t toff = opaque_off(static_cast<uint32_t>((t / CPR) * (L * L * Sh::SZ) + (t % CPR) * 16));
-#pragma unroll
-  for (int k = 0; k < Sh::CPT; ++k) {
-    const uint32_t off = toff + static_cast<uint32_t>(k * (Sh::NT / CPR) * (L * L * Sh::SZ));
-    __builtin_amdgcn_global_load_lds((gptr_t)(g + off), (lptr_t)(lds + dst + (k * Sh::NT + w * 64) * 16), 16, 0, AUX);
-  }
-}
-
-// wait for this wave's LDS-DMA loads, then for every wave's
-__device__ __forceinline__ void stage_wait() {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-}
 
 // Thread t owns lines (row0 + l*RPT, col) for l < LPT, with row0 = t / L.
 //
@@ -345,27 +307,39 @@ __device__ __forceinline__ void fused_inverse(typename cx<T>::t (*x)[L], typenam
 // phase costs about one memory latency instead of one per batch.
 constexpr int kB = 8;
 
-// rho = conj(u_m) u_n in layout A, both orbitals staged through LDS quarter
-// by quarter (one memory round trip per quarter).
+// rho = conj(u_m) u_n, both orbitals double-buffered.
 template <typename T, int L>
 __device__ __forceinline__ void load_codensity(typename cx<T>::t (*x)[L], const typename cx<T>::t* __restrict__ bm,
-                                               const typename cx<T>::t* __restrict__ bn, unsigned char* lds,
-                                               int row0, int col) {
+                                               const typename cx<T>::t* __restrict__ bn, uint32_t toff) {
   using C = typename cx<T>::t;
   using Sh = FusedShape<T, L>;
+  constexpr int E = Sh::LPT * L;
+  constexpr int NB = E / kB;
+  static_assert(E % kB == 0, "batch size must divide the thread's elements");
+  C mb[2][kB], nb[2][kB];
 #pragma unroll
-  for (int q = 0; q < Sh::NQ; ++q) {
-    stage_quarter<T, L, 0>(bm, q, lds, 0);
-    stage_quarter<T, L, 0>(bn, q, lds, Sh::QBYTES);
-    stage_wait();
+  for (int j = 0; j < kB; ++j) {
+    const uint32_t a = toff + (j / L) * (Sh::RPT * L * L) + (j % L) * L;
+    mb[0][j] = bm[a];
+    nb[0][j] = bn[a];
+  }
 #pragma unroll
-    for (int l = 0; l < Sh::LPT; ++l) {
-      const uint32_t b = opaque_off(static_cast<uint32_t>((row0 + l * Sh::RPT) * Sh::RUN + col * Sh::SZ));
+  for (int b = 0; b < NB; ++b) {
+    if (b + 1 < NB) {
 #pragma unroll
-      for (int i = 0; i < Sh::QL; ++i)
-        x[l][q * Sh::QL + i] = cmulconj(lds_at<C>(lds, b + i * L * Sh::SZ), lds_at<C>(lds, b + Sh::QBYTES + i * L * Sh::SZ));
+      for (int j = 0; j < kB; ++j) {
+        const int e = (b + 1) * kB + j;
+        const uint32_t a = toff + (e / L) * (Sh::RPT * L * L) + (e % L) * L;
+        mb[(b + 1) & 1][j] = bm[a];
+        nb[(b + 1) & 1][j] = bn[a];
+      }
     }
-    __syncthreads();
+    mem_fence_compiler();
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int e = b * kB + j;
+      x[e / L][e % L] = cmulconj(mb[b & 1][j], nb[b & 1][j]);
+    }
   }
 }
 
@@ -441,8 +415,7 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     const int pkm = r.x * nbands + r.y;
     const size_t om = static_cast<size_t>(pkm) * bs;
     C x[LPT][L];
-    load_codensity<T, L>(x, psi + opaque_idx(om), psi + opaque_idx(on), reinterpret_cast<unsigned char*>(s), row0,
-                         col);
+    load_codensity<T, L>(x, psi + opaque_idx(om), psi + opaque_idx(on), opaque_off(toff0));
     // warm L2 with the next partner's orbital and kernel table while the FFTs run
     Prefetch<T> pf{nullptr, nullptr, junk};
     if (p + 1 < p1) {
@@ -456,31 +429,42 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     const T coef = static_cast<T>(-kw[r.x] * occ[pkm] * f);
     const C* bm = psi + opaque_idx(om);
     C* bo = dst + opaque_idx(od);
+    const uint32_t toff = opaque_off(toff0);
+    // accumulate: u_m (and the running output) in double-buffered batches
+    constexpr int E = LPT * L;
+    constexpr int kA = 4;  // smaller batches here: x, u_m and the output are live together
+    constexpr int NB = E / kA;
+    C mb[2][kA], ob[2][kA];
     const bool rmw = !Sh::ACC_REG && p > p0;
-    unsigned char* lds = reinterpret_cast<unsigned char*>(s);
-    // accumulate: u_m (and the running output) staged through LDS by quarters;
-    // the output is re-read past L1 (sc0) since other lanes wrote it
 #pragma unroll
-    for (int q = 0; q < Sh::NQ; ++q) {
-      stage_quarter<T, L, 0>(bm, q, lds, 0);
-      if (rmw) stage_quarter<T, L, 1>(bo, q, lds, Sh::QBYTES);
-      stage_wait();
+    for (int j = 0; j < kA; ++j) {
+      const uint32_t a = toff + (j / L) * (Sh::RPT * LL) + (j % L) * L;
+      mb[0][j] = bm[a];
+      if (rmw) ob[0][j] = bo[a];
+    }
 #pragma unroll
-      for (int l = 0; l < LPT; ++l) {
-        const uint32_t b = opaque_off(static_cast<uint32_t>((row0 + l * Sh::RPT) * Sh::RUN + col * Sh::SZ));
-        const uint32_t go = static_cast<uint32_t>((row0 + l * Sh::RPT) * LL + col);
+    for (int b = 0; b < NB; ++b) {
+      if (b + 1 < NB) {
 #pragma unroll
-        for (int i = 0; i < Sh::QL; ++i) {
-          const int j2 = q * Sh::QL + i;
-          const C w = cscale(cmul(lds_at<C>(lds, b + i * L * Sh::SZ), x[l][j2]), coef);
-          if constexpr (Sh::ACC_REG) {
-            acc[l][j2] = cadd(acc[l][j2], w);
-          } else {
-            bo[go + j2 * L] = rmw ? cadd(lds_at<C>(lds, b + Sh::QBYTES + i * L * Sh::SZ), w) : w;
-          }
+        for (int j = 0; j < kA; ++j) {
+          const int e = (b + 1) * kA + j;
+          const uint32_t a = toff + (e / L) * (Sh::RPT * LL) + (e % L) * L;
+          mb[(b + 1) & 1][j] = bm[a];
+          if (rmw) ob[(b + 1) & 1][j] = bo[a];
         }
       }
-      __syncthreads();
+      mem_fence_compiler();
+#pragma unroll
+      for (int j = 0; j < kA; ++j) {
+        const int e = b * kA + j;
+        const C w = cscale(cmul(mb[b & 1][j], x[e / L][e % L]), coef);
+        if constexpr (Sh::ACC_REG) {
+          acc[e / L][e % L] = cadd(acc[e / L][e % L], w);
+        } else {
+          const uint32_t a = toff + (e / L) * (Sh::RPT * LL) + (e % L) * L;
+          bo[a] = rmw ? cadd(ob[b & 1][j], w) : w;
+        }
+      }
     }
   }
   if constexpr (Sh::ACC_REG) {
@@ -518,7 +502,7 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_energy_fused(
     C x[LPT][L];
     load_codensity<T, L>(x, psi + opaque_idx(static_cast<size_t>(pr.kp * nbands + pr.m) * bs),
                          psi + opaque_idx(static_cast<size_t>(pr.k * nbands + pr.n) * bs),
-                         reinterpret_cast<unsigned char*>(s), row0, col);
+                         opaque_off(static_cast<uint32_t>(row0 * LL + col)));
     fused_forward<T, L>(x, s, row0, col);
     // |P|^2 in place (x[.].x), then weight by the table
 #pragma unroll

@@ -1,0 +1,184 @@
+"""Short text summaries of rocprofv3 output for the library's kernels.
+
+  python -m paper_1111_0716_amd.profile_summary trace DIR --title T --command C [--out FILE]
+      per-kernel calls / average / share from DIR/*_kernel_stats.csv
+      (a `rocprofv3 --kernel-trace --stats --output-format csv` run)
+
+  python -m paper_1111_0716_amd.profile_summary traffic --fetch DIR --write DIR
+         --kernel SUBSTR --copy-bytes B --kind KIND --units-per-launch U
+         --bytes-per-unit A --command C [--command C2] [--out FILE]
+      HBM bytes per launch of the kernel whose name contains SUBSTR, from two
+      `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs; each counter is scaled by
+      the factor that makes the same counter read B bytes on the largest plain
+      device-to-device copy (`__amd_rocclr_copyBuffer`) of the same run.
+
+The traffic summary carries machine-readable lines (`key: value`) that
+bench.py reads back; `sources_sha256` fingerprints the kernel's source files
+so that a later change of the kernel voids the figure.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+import shlex
+import sys
+
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+# source files of each kernel kind (the .hip file and the headers it includes)
+KIND_SOURCES = {
+    "fused": ["pair_fused.hip", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "energy_fused": ["pair_fused.hip", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "plane": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
+    "pencil": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
+    "accumulate": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
+    "energy_plane": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
+    "energy_pencil": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
+    "overlap": ["overlap_mfma.hip", "fft_lds.hpp", "fock_internal.hpp"],
+}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def sources_sha256(kind):
+    h = hashlib.sha256()
+    for name in KIND_SOURCES[kind]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def short_name(name):
+    """Kernel name without the argument list: `void ns::k<T, 32>(...)` -> `ns::k<T, 32>`."""
+    name = re.sub(r"^void ", "", name).replace("(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def _one(pattern):
+    files = sorted(glob.glob(pattern, recursive=True))
+    if not files:
+        raise SystemExit(f"no file matches {pattern}")
+    return files[0]
+
+
+def read_kernel_stats(d):
+    with open(_one(os.path.join(d, "**", "*kernel_stats.csv"))) as f:
+        return list(csv.DictReader(f))
+
+
+def read_counter(d, counter):
+    """[(kernel name, value)] per dispatch, in dispatch order."""
+    rows = []
+    with open(_one(os.path.join(d, "**", "*counter_collection.csv"))) as f:
+        for r in csv.DictReader(f):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def trace_summary(d, title, command):
+    rows = read_kernel_stats(d)
+    out = [f"# {title}", "", "Command (from the repository root):", "", "```", command, "```", "",
+           "| kernel | calls | average (ms) | min (ms) | max (ms) | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} % |")
+    return "\n".join(out) + "\n"
+
+
+def calibrated(d, counter, kernel, copy_bytes):
+    """(scaled bytes per kernel dispatch, kernel dispatches, factor, copy KiB read)."""
+    rows = read_counter(d, counter)
+    copies = [v for k, v in rows if k == COPY_KERNEL]
+    if not copies:
+        raise SystemExit(f"{d}: no {COPY_KERNEL} dispatch to calibrate {counter} against")
+    copy_kib = max(copies)
+    factor = copy_bytes / (copy_kib * 1024.0)
+    vals = [v for k, v in rows if kernel in k]
+    if not vals:
+        raise SystemExit(f"{d}: no dispatch of a kernel containing {kernel!r}")
+    # the first dispatch is a warm-up (cold caches, first touch); average the rest
+    use = vals[1:] if len(vals) > 1 else vals
+    return sum(use) / len(use) * 1024.0 * factor, len(use), factor, copy_kib
+
+
+def traffic_summary(a, argv):
+    fb, nf, ff, fk = calibrated(a.fetch, "FETCH_SIZE", a.kernel, a.copy_bytes)
+    wb, nw, fw, wk = calibrated(a.write, "WRITE_SIZE", a.kernel, a.copy_bytes)
+    alg = a.units_per_launch * a.bytes_per_unit
+    total = fb + wb
+    lines = [f"# HBM traffic: {a.title}", "",
+             "Commands (from the repository root; one counter per run):", "", "```", *a.command,
+             "python -m paper_1111_0716_amd.profile_summary " + shlex.join(argv), "```", "",
+             f"Calibration: the largest `{COPY_KERNEL}` dispatch of each run is a device-to-device copy of "
+             f"{a.copy_bytes} bytes, so it must read and write that many bytes.", "",
+             "| counter | copy reads (KiB) | scale factor | kernel dispatches averaged | scaled bytes per launch |",
+             "|---|---|---|---|---|",
+             f"| FETCH_SIZE | {fk:.1f} | {ff:.4f} | {nf} | {fb:.4e} |",
+             f"| WRITE_SIZE | {wk:.1f} | {fw:.4f} | {nw} | {wb:.4e} |", "",
+             f"Algorithmic bytes per launch: {a.units_per_launch} units x {a.bytes_per_unit} B = {alg:.4e} B; "
+             f"measured / algorithmic = {total / alg:.3f}.", "",
+             f"kind: {a.kind}",
+             f"kernel: {a.kernel}",
+             f"fetch_bytes_per_launch: {fb:.6e}",
+             f"write_bytes_per_launch: {wb:.6e}",
+             f"traffic_bytes_per_launch: {total:.6e}",
+             f"sources_sha256: {sources_sha256(a.kind)}", ""]
+    return "\n".join(lines)
+
+
+def read_traffic(path, kind):
+    """Scaled HBM bytes per launch from a traffic summary, or None when the
+    file is absent or the kernel's sources changed since it was taken."""
+    try:
+        with open(path) as f:
+            kv = dict(re.findall(r"^(\w+): (\S+)$", f.read(), flags=re.M))
+    except OSError:
+        return None
+    if kv.get("kind") != kind or kv.get("sources_sha256") != sources_sha256(kind):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("dir")
+    t.add_argument("--title", required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--out")
+    c = sub.add_parser("traffic")
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--kind", required=True, choices=sorted(KIND_SOURCES))
+    c.add_argument("--copy-bytes", type=int, required=True)
+    c.add_argument("--units-per-launch", type=float, required=True)
+    c.add_argument("--bytes-per-unit", type=float, required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", action="append", required=True)
+    c.add_argument("--out")
+    argv = sys.argv[1:] if argv is None else list(argv)
+    a = ap.parse_args(argv)
+    text = trace_summary(a.dir, a.title, a.command) if a.mode == "trace" else traffic_summary(a, argv)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(text)
+    else:
+        sys.stdout.write(text)
+
+
+if __name__ == "__main__":
+    main()
