@@ -134,11 +134,13 @@ def test_fp64_results_are_bitwise_reproducible(device):
     assert ex2.item() == g["ex"]
 
 
-@pytest.mark.parametrize("prec", ["c128", "c64"])
-def test_backward_matches_oracle_gradient(prec, device):
+@pytest.mark.parametrize("grid,prec", [((10, 12, 9), "c128"), ((10, 12, 9), "c64"), ((16, 16, 16), "c64"),
+                                       ((24, 24, 24), "c64"), ((16, 16, 16), "c128")])
+def test_backward_matches_oracle_gradient(grid, prec, device):
     import torch
 
-    inst = inputs.small_instance(grid=(10, 12, 9), kmesh=(2, 1, 1), nbands=3, seed=(203, 0), full_grid=True)
+    log(f"backward grid={grid} prec={prec}")
+    inst = inputs.small_instance(grid=grid, kmesh=(2, 1, 1), nbands=3, seed=(203, grid[0]), full_grid=True)
     if prec == "c64":
         inst = inst.astype(np.complex64)
     g = run_gpu(inst, prec, device)
@@ -224,3 +226,16 @@ def test_alpha_boron_config_sampled_outputs(device):
     ex64 = plan64.fock_energy([psi64], [occ64]).item()
     log(f"  E32 {g['ex']:.12f}  E64 {ex64:.12f}")
     assert abs(g["ex"] - ex64) <= 1e-6 * abs(ex64)
+
+
+@pytest.mark.parametrize("kp", [[[0, 0], [0, 1], [1, 0], [1, 1]], [[0, 0], [1, 1]], [[0, 1], [1, 0], [1, 1]]])
+def test_whole_pair_explicit_k_pairs(kp, device):
+    """Explicit k-pair lists on a whole-pair grid: the full set listed
+    explicitly, a diagonal-only set, and a set without (0, 0)."""
+    inst = inputs.small_instance(grid=(16, 16, 16), kmesh=(2, 1, 1), nbands=3, seed=(207, len(kp))).astype(np.complex64)
+    kp = np.array(kp, dtype=np.int32)
+    g = run_gpu(inst, "c64", device, kpairs=kp)
+    o = Oracle.from_instance(inst, kpairs=kp)
+    vref, eref = o.apply(inst.psi.astype(np.complex128), inst.occ)
+    assert band_err(g["vx"], vref) <= 1e-5
+    assert abs(g["ex"] - eref) <= 1e-6 * abs(eref)
