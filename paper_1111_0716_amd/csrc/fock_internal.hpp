@@ -54,6 +54,7 @@ struct Instance {
   std::vector<std::vector<int>> kpartners;  // k -> list of k'
   bool symmetric = true;                     // (k, k') listed iff (k', k) listed
   bool fused = false;                        // whole-pair path (cubic grid that fits one CU)
+  bool reg = false;                          // three-pass path with register-line kernels (cubic)
   int nbands;
   int64_t band_stride;
   double mu;
@@ -142,6 +143,12 @@ size_t fused_lds_bytes(fock_precision prec, int L);
 int fused_threads(fock_precision prec, int L);
 size_t overlap_scratch_bytes(const Instance& in);
 void prepare_fused_kernels(fock_precision prec, int lim);
+bool reg_supported(fock_precision prec, const int grid[3]);
+size_t reg_lds_bytes(fock_precision prec, int L);
+void prepare_reg_kernels(fock_precision prec, int lim);
+hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                                  const double* gscale, double hscale, bool backward);
+hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
                               const double* gscale, double hscale, bool backward);
 hipError_t launch_fused_energy(const Plan& p, const Batch& b, const void* psi);

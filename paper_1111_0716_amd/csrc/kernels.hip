@@ -285,6 +285,7 @@ hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const d
                          const double* gscale, double hscale, bool backward) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[b.inst];
+  if (in.reg) return launch_reg_apply_batch(p, b, psi, occ, out, gscale, hscale, backward);
   const Geo g = geo_of(in);
   const C* tw = reinterpret_cast<const C*>(p.ws + p.tw_off);
   const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
@@ -314,6 +315,7 @@ template <typename T>
 hipError_t energy_batch_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[b.inst];
+  if (in.reg) return launch_reg_energy_batch(p, b, psi, occ);
   const Geo g = geo_of(in);
   const C* tw = reinterpret_cast<const C*>(p.ws + p.tw_off);
   const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
@@ -380,6 +382,7 @@ hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
   if (e != hipSuccess) return e;
   *max_lds = static_cast<size_t>(lim);
   prepare_fused_kernels(prec, lim - 256);
+  prepare_reg_kernels(prec, lim - 64);
   if (lim > 65536) {
     if (prec == FOCK_C128)
       allow_large_lds<double>(lim - 64);

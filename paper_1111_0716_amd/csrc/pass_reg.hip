@@ -1,0 +1,378 @@
+// Three-pass kernels with register-line FFTs for cubic grids L^3 that do not
+// take the whole-pair kernels (L in {24, 32, 40, 48, 64, 72} FP32, L in
+// {24, 32} FP64; larger FP64 lines would spill).  Same passes and batching as the LDS-Stockham kernels (paper,
+// "Our Implementation": the band-pair loop on the GPU; NSIM-like blocks of
+// outputs x partners), but every 1-D transform runs in one thread's registers
+// on a whole line (reg_fft.hpp), a plane switches axes through one padded LDS
+// transpose, and the pair buffer T is laid out [j1][c3][c2] (c2 fastest) so
+// that every global access of every pass is coalesced across the lanes:
+//
+//   plane   thread (plane p, j3): column u along axis 2 -> FFT_2 -> LDS ->
+//           thread (p, c2): row along axis 3 -> FFT_3 -> T[j1][c3][c2]
+//   pencil  thread (c3, c2): line along axis 1 -> FFT_1 -> x v_q/N -> IFFT_1
+//           (apply; the table is stored [c1][c3][c2]) or FP64 sum v |P|^2
+//   acc     thread (p, c2): row of T -> IFFT_3 -> LDS -> thread (p, j3):
+//           column -> IFFT_2 -> acc += -w' f' u_m W in registers, for every
+//           partner of the batch; one write (or add) of the output per batch
+#include <algorithm>
+
+#include "fft_lds.hpp"
+#include "fock_internal.hpp"
+#include "reg_fft.hpp"
+
+namespace fock {
+
+template <typename T, int L>
+struct RegShape {
+  using C = typename cx<T>::t;
+  static constexpr int LP = L + 1;  // padded LDS row
+  static constexpr int PLANE_LDS = L * LP * static_cast<int>(sizeof(C));
+  // planes per workgroup: about 256 threads, within 150 KiB of LDS
+  static constexpr int PL0 = (256 / L) > 0 ? (256 / L) : 1;
+  static constexpr int PL = (PL0 * PLANE_LDS <= 150 * 1024) ? PL0 : ((150 * 1024) / PLANE_LDS > 0 ? (150 * 1024) / PLANE_LDS : 1);
+  static constexpr int NTP = PL * L;             // threads of the plane and accumulate passes
+  static constexpr int NG = (L + PL - 1) / PL;   // plane groups
+  static constexpr int LDS = PL * PLANE_LDS;
+  static constexpr int NTL = 256;                // threads of the pencil pass (one line each)
+  static constexpr int NLB = (L * L + NTL - 1) / NTL;  // line blocks per pair
+};
+
+// ---------------------------------------------------------------------------
+// plane pass: rho = conj(u_m) u_n, FFT along axes 2 and 3, T[j1][c3][c2]
+// ---------------------------------------------------------------------------
+template <typename T, int L, bool EXPLICIT>
+__global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_plane_reg(int nbands, long long bs,
+                                                                    const typename cx<T>::t* __restrict__ psi, int o0,
+                                                                    int nP, const int2* __restrict__ parts,
+                                                                    const PairRef* __restrict__ pairs,
+                                                                    typename cx<T>::t* __restrict__ tbuf) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  constexpr int LL = L * L;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
+  const int j1 = blockIdx.x * Sh::PL + pl;
+  const bool valid = j1 < L;
+  const int pi = blockIdx.y;
+  int okn, pkm;
+  if (EXPLICIT) {
+    const PairRef pr = pairs[pi];
+    okn = pr.k * nbands + pr.n;
+    pkm = pr.kp * nbands + pr.m;
+  } else {
+    const int o = pi / nP, p = pi - o * nP;
+    okn = o0 + o;
+    const int2 r = parts[p];
+    pkm = r.x * nbands + r.y;
+  }
+  C x[L];
+  if (valid) {
+    const C* a = psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
+    const C* b = psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col;
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) x[j2] = cmulconj(b[j2 * L], a[j2 * L]);
+  } else {
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) x[j2] = C{T(0), T(0)};
+  }
+  reg_fft<C, L, -1>(x);  // axis 2: x[c2] at (j1, c2, j3 = col)
+  C* sp = s + pl * L * Sh::LP;
+#pragma unroll
+  for (int c2 = 0; c2 < L; ++c2) sp[c2 * Sh::LP + col] = x[c2];
+  __syncthreads();
+#pragma unroll
+  for (int j3 = 0; j3 < L; ++j3) x[j3] = sp[col * Sh::LP + j3];  // thread now holds c2 = col
+  reg_fft<C, L, -1>(x);  // axis 3: x[c3]
+  if (valid) {
+    C* dst = tbuf + (static_cast<size_t>(pi) * L + j1) * LL + col;
+#pragma unroll
+    for (int c3 = 0; c3 < L; ++c3) dst[c3 * L] = x[c3];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pencil pass, apply: FFT_1, x v_q/N, IFFT_1 on lines (c3, c2) of T
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_pencil_apply_reg(int nbands, int nk, int o0, int nP,
+                                                          const int2* __restrict__ parts, const int* __restrict__ qmap,
+                                                          typename cx<T>::t* __restrict__ tbuf,
+                                                          const T* __restrict__ vtab) {
+  using C = typename cx<T>::t;
+  constexpr int LL = L * L;
+  const int l = blockIdx.x * 256 + threadIdx.x;  // line (c3, c2) = l
+  const int pi = blockIdx.y;
+  if (l >= LL) return;  // no barrier in this kernel
+  const int o = pi / nP, p = pi - o * nP;
+  const int ok = (o0 + o) / nbands;
+  const int q = qmap[ok * nk + parts[p].x];
+  C* base = tbuf + static_cast<size_t>(pi) * LL * L + l;
+  C x[L];
+#pragma unroll
+  for (int j1 = 0; j1 < L; ++j1) x[j1] = base[static_cast<size_t>(j1) * LL];
+  reg_fft<C, L, -1>(x);
+  const T* v = vtab + static_cast<size_t>(q) * LL * L + l;
+#pragma unroll
+  for (int c1 = 0; c1 < L; ++c1) x[c1] = cscale(x[c1], v[static_cast<size_t>(c1) * LL]);
+  reg_fft<C, L, +1>(x);
+#pragma unroll
+  for (int j1 = 0; j1 < L; ++j1) base[static_cast<size_t>(j1) * LL] = x[j1];
+}
+
+// ---------------------------------------------------------------------------
+// pencil pass, energy: FFT_1 and sum v_q/N |P|^2 in FP64 per line block
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_pencil_energy_reg(const PairRef* __restrict__ pairs,
+                                                           const typename cx<T>::t* __restrict__ tbuf,
+                                                           const T* __restrict__ vtab, double* __restrict__ epart) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  constexpr int LL = L * L;
+  __shared__ double red[4];
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  const int pi = blockIdx.y;
+  double e = 0.0;
+  if (l < LL) {
+    const int q = pairs[pi].q;
+    const C* base = tbuf + static_cast<size_t>(pi) * LL * L + l;
+    C x[L];
+#pragma unroll
+    for (int j1 = 0; j1 < L; ++j1) x[j1] = base[static_cast<size_t>(j1) * LL];
+    reg_fft<C, L, -1>(x);
+    const T* v = vtab + static_cast<size_t>(q) * LL * L + l;
+#pragma unroll
+    for (int c1 = 0; c1 < L; ++c1) {
+      const double px = static_cast<double>(x[c1].x), py = static_cast<double>(x[c1].y);
+      e += static_cast<double>(v[static_cast<size_t>(c1) * LL]) * (px * px + py * py);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * Sh::NLB + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// ---------------------------------------------------------------------------
+// accumulate pass: per (output, plane group), every partner of the batch
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_acc_reg(int nbands, long long bs, int o0, int nP,
+                                                                  const int2* __restrict__ parts,
+                                                                  const typename cx<T>::t* __restrict__ tbuf,
+                                                                  const typename cx<T>::t* __restrict__ psi,
+                                                                  const double* __restrict__ occ,
+                                                                  const double* __restrict__ kw,
+                                                                  typename cx<T>::t* __restrict__ out, int first,
+                                                                  const double* __restrict__ gscale, double hscale,
+                                                                  int backward) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  constexpr int LL = L * L;
+  extern __shared__ unsigned char smem_raw[];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
+  const int j1 = blockIdx.x * Sh::PL + pl;
+  const bool valid = j1 < L;
+  const int o = blockIdx.y;
+  C* sp = s + pl * L * Sh::LP;
+  C acc[L];
+#pragma unroll
+  for (int j2 = 0; j2 < L; ++j2) acc[j2] = C{T(0), T(0)};
+  for (int p = 0; p < nP; ++p) {
+    const int2 r = parts[p];
+    C x[L];
+    if (valid) {
+      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * L + static_cast<size_t>(j1) * LL + col;
+#pragma unroll
+      for (int c3 = 0; c3 < L; ++c3) x[c3] = src[c3 * L];  // row (j1, c2 = col)
+    } else {
+#pragma unroll
+      for (int c3 = 0; c3 < L; ++c3) x[c3] = C{T(0), T(0)};
+    }
+    reg_fft<C, L, +1>(x);  // inverse axis 3: x[j3] at (j1, c2 = col)
+    __syncthreads();       // the previous partner's columns have been read
+#pragma unroll
+    for (int j3 = 0; j3 < L; ++j3) sp[j3 * Sh::LP + col] = x[j3];
+    __syncthreads();
+#pragma unroll
+    for (int c2 = 0; c2 < L; ++c2) x[c2] = sp[col * Sh::LP + c2];  // column (j1, j3 = col)
+    reg_fft<C, L, +1>(x);  // inverse axis 2: x[j2]
+    if (valid) {
+      const T coef = static_cast<T>(-kw[r.x] * occ[r.x * nbands + r.y]);
+      const C* um = psi + static_cast<size_t>(r.x * nbands + r.y) * bs + static_cast<size_t>(j1) * LL + col;
+#pragma unroll
+      for (int j2 = 0; j2 < L; ++j2) {
+        const C w = cmul(um[j2 * L], x[j2]);
+        acc[j2].x += coef * w.x;
+        acc[j2].y += coef * w.y;
+      }
+    }
+  }
+  if (!valid) return;  // no barrier after this point
+  const int okn = o0 + o;
+  double f = hscale;
+  if (gscale) f *= gscale[0];
+  if (backward) f *= kw[okn / nbands] * occ[okn];
+  const T ft = static_cast<T>(f);
+  C* dst = out + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
+#pragma unroll
+  for (int j2 = 0; j2 < L; ++j2) {
+    C v = cscale(acc[j2], ft);
+    if (!first) v = cadd(dst[j2 * L], v);
+    dst[j2 * L] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T, int L>
+hipError_t reg_apply_L(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                       const double* gscale, double hscale, bool backward) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  const Instance& in = p.inst[b.inst];
+  const long long bs = static_cast<long long>(in.band_stride);
+  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
+  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
+  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
+  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
+  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
+  p.prof.begin(FOCK_K_PLANE, p.stream);
+  hipLaunchKernelGGL((k_plane_reg<T, L, false>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
+                     in.nbands, bs, static_cast<const C*>(psi), b.o0, b.nP, parts,
+                     static_cast<const PairRef*>(nullptr), tbuf);
+  p.prof.end(FOCK_K_PLANE, p.stream);
+  p.prof.begin(FOCK_K_PENCIL, p.stream);
+  hipLaunchKernelGGL((k_pencil_apply_reg<T, L>), dim3(Sh::NLB, b.npairs), dim3(256), 0, p.stream, in.nbands, in.nk,
+                     b.o0, b.nP, parts, qmap, tbuf, vtab);
+  p.prof.end(FOCK_K_PENCIL, p.stream);
+  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
+  hipLaunchKernelGGL((k_acc_reg<T, L>), dim3(Sh::NG, b.nO), dim3(Sh::NTP), Sh::LDS, p.stream, in.nbands, bs, b.o0,
+                     b.nP, parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ, kw,
+                     static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
+  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t reg_energy_L(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  const Instance& in = p.inst[b.inst];
+  const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
+  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
+  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
+  double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
+  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
+  hipLaunchKernelGGL((k_plane_reg<T, L, true>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
+                     in.nbands, static_cast<long long>(in.band_stride), static_cast<const C*>(psi), 0, 1,
+                     static_cast<const int2*>(nullptr), pairs, tbuf);
+  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
+  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
+  hipLaunchKernelGGL((k_pencil_energy_reg<T, L>), dim3(Sh::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
+                     static_cast<const C*>(tbuf), vtab, epart);
+  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
+  return launch_energy_reduce(p, b, occ, Sh::NLB);
+}
+
+// the lengths with register-line kernels, per precision
+#define FOCK_REG_F32(X) X(24) X(32) X(40) X(48) X(64) X(72)
+#define FOCK_REG_F64(X) X(24) X(32)
+
+template <typename T>
+hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                       const double* gscale, double hscale, bool backward) {
+  const int L = p.inst[b.inst].grid[0];
+#define CASE(N) \
+  case N: return reg_apply_L<T, N>(p, b, psi, occ, out, gscale, hscale, backward);
+  if constexpr (sizeof(T) == 4) {
+    switch (L) { FOCK_REG_F32(CASE) default: break; }
+  } else {
+    switch (L) { FOCK_REG_F64(CASE) default: break; }
+  }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+  const int L = p.inst[b.inst].grid[0];
+#define CASE(N) \
+  case N: return reg_energy_L<T, N>(p, b, psi, occ);
+  if constexpr (sizeof(T) == 4) {
+    switch (L) { FOCK_REG_F32(CASE) default: break; }
+  } else {
+    switch (L) { FOCK_REG_F64(CASE) default: break; }
+  }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int L>
+void reg_lds_attr(int lim) {
+  const void* fs[] = {reinterpret_cast<const void*>(&k_plane_reg<T, L, false>),
+                      reinterpret_cast<const void*>(&k_plane_reg<T, L, true>),
+                      reinterpret_cast<const void*>(&k_acc_reg<T, L>)};
+  for (const void* f : fs)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+}
+
+}  // namespace
+
+bool reg_supported(fock_precision prec, const int grid[3]) {
+  if (grid[0] != grid[1] || grid[0] != grid[2]) return false;
+  switch (grid[0]) {
+    case 24: case 32: return true;
+    case 40: case 48: case 64: case 72: return prec == FOCK_C64;
+    default: return false;
+  }
+}
+
+size_t reg_lds_bytes(fock_precision prec, int L) {
+  size_t r = 0;
+#define CASE(N) \
+  case N: r = RegShape<float, N>::LDS; break;
+  if (prec == FOCK_C64) {
+    switch (L) { FOCK_REG_F32(CASE) default: break; }
+  }
+#undef CASE
+#define CASE(N) \
+  case N: r = RegShape<double, N>::LDS; break;
+  if (prec == FOCK_C128) {
+    switch (L) { FOCK_REG_F64(CASE) default: break; }
+  }
+#undef CASE
+  return r;
+}
+
+int reg_energy_slots(fock_precision prec, int L) {
+  (void)prec;
+  return (L * L + 255) / 256;
+}
+
+void prepare_reg_kernels(fock_precision prec, int lim) {
+#define CASE(N) reg_lds_attr<float, N>(lim);
+  if (prec == FOCK_C64) { FOCK_REG_F32(CASE) }
+#undef CASE
+#define CASE(N) reg_lds_attr<double, N>(lim);
+  if (prec == FOCK_C128) { FOCK_REG_F64(CASE) }
+#undef CASE
+}
+
+hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                                  const double* gscale, double hscale, bool backward) {
+  return p.prec == FOCK_C128 ? reg_apply_t<double>(p, b, psi, occ, out, gscale, hscale, backward)
+                             : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward);
+}
+
+hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+  return p.prec == FOCK_C128 ? reg_energy_t<double>(p, b, psi, occ) : reg_energy_t<float>(p, b, psi, occ);
+}
+
+}  // namespace fock

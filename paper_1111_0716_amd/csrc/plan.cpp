@@ -213,7 +213,12 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   }
   const char* nofused = std::getenv("FOCK_NO_FUSED");
   const bool no_fused = tn.no_fused != 0 || (nofused && *nofused && *nofused != '0');
-  for (auto& in : p->inst) in.fused = fused_supported(prec, in.grid) && !no_fused;
+  const char* noreg = std::getenv("FOCK_NO_REG");
+  const bool no_reg = noreg && *noreg && *noreg != '0';
+  for (auto& in : p->inst) {
+    in.fused = fused_supported(prec, in.grid) && !no_fused;
+    in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
+  }
 
   // ---- batch shapes ----
   const size_t tbuf_target = (tn.tbuf_mb > 0 ? static_cast<size_t>(tn.tbuf_mb) : env_mb("FOCK_TBUF_MB", 1024)) << 20;
@@ -380,7 +385,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->total_bytes = off;
   for (const auto& in : p->inst) {
     const size_t plane = static_cast<size_t>(in.grid[1]) * in.grid[2], tile = static_cast<size_t>(in.grid[0]) * in.grid[2];
-    const size_t need = in.fused ? fused_lds_bytes(prec, in.grid[0]) + 256 : std::max(plane, tile) * p->csize + 64;
+    const size_t need = in.fused ? fused_lds_bytes(prec, in.grid[0]) + 256
+                        : in.reg ? reg_lds_bytes(prec, in.grid[0]) + 64
+                                 : std::max(plane, tile) * p->csize + 64;
     p->lds_needed = std::max(p->lds_needed, need);
   }
   p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size());
@@ -419,6 +426,15 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
           for (int c2 = 0; c2 < L; ++c2)
             for (int c3 = 0; c3 < L; ++c3)
               r[(static_cast<size_t>(c3) * L + c2) * L + c1] = t[(static_cast<size_t>(c1) * L + c2) * L + c3];
+        t.swap(r);
+      } else if (in.reg) {
+        // register-line three-pass path reads the table as [c1][c3][c2]
+        const int L = in.grid[0];
+        std::vector<double> r(t.size());
+        for (int c1 = 0; c1 < L; ++c1)
+          for (int c2 = 0; c2 < L; ++c2)
+            for (int c3 = 0; c3 < L; ++c3)
+              r[(static_cast<size_t>(c1) * L + c3) * L + c2] = t[(static_cast<size_t>(c1) * L + c2) * L + c3];
         t.swap(r);
       }
       if (prec == FOCK_C128) {

@@ -30,13 +30,13 @@ import sys
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 # source files of each kernel kind (the .hip file and the headers it includes)
 KIND_SOURCES = {
-    "fused": ["pair_fused.hip", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "energy_fused": ["pair_fused.hip", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "plane": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
-    "pencil": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
-    "accumulate": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
-    "energy_plane": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
-    "energy_pencil": ["kernels.hip", "fft_lds.hpp", "fock_internal.hpp"],
+    "fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "energy_fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "accumulate": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "energy_plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "energy_pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
     "overlap": ["overlap_mfma.hip", "fft_lds.hpp", "fock_internal.hpp"],
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"

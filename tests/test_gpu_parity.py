@@ -72,6 +72,11 @@ CASES = [
     ((8, 6, 10), (2, 2, 1), 3, True, "c64"),
     ((64, 64, 64), (1, 1, 1), 2, False, "c64"),
     ((72, 72, 72), (1, 1, 1), 1, False, "c64"),
+    # register-line three-pass path (cubic grids)
+    ((24, 24, 24), (2, 1, 1), 3, False, "c128"),
+    ((32, 32, 32), (1, 2, 1), 2, True, "c128"),
+    ((40, 40, 40), (1, 1, 1), 2, False, "c64"),
+    ((48, 48, 48), (2, 1, 1), 2, True, "c64"),
     # whole-pair path (cubic grids that fit one compute unit)
     ((32, 32, 32), (1, 1, 1), 3, False, "c64"),
     ((32, 32, 32), (2, 1, 1), 2, True, "c64"),
@@ -239,3 +244,22 @@ def test_whole_pair_explicit_k_pairs(kp, device):
     vref, eref = o.apply(inst.psi.astype(np.complex128), inst.occ)
     assert band_err(g["vx"], vref) <= 1e-5
     assert abs(g["ex"] - eref) <= 1e-6 * abs(eref)
+
+
+@pytest.mark.parametrize("grid,prec", [((32, 32, 32), "c128"), ((24, 24, 24), "c128"), ((48, 48, 48), "c64"),
+                                       ((64, 64, 64), "c64")])
+def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
+    """The register-line three-pass kernels and the LDS-Stockham three-pass
+    kernels compute the same operator and energy (FP64: to rounding)."""
+    log(f"register-line vs LDS grid={grid} prec={prec}")
+    inst = inputs.small_instance(grid=grid, kmesh=(2, 1, 1), nbands=2, seed=(208, grid[0]))
+    if prec == "c64":
+        inst = inst.astype(np.complex64)
+    reg = run_gpu(inst, prec, device)
+    monkeypatch.setenv("FOCK_NO_REG", "1")
+    lds = run_gpu(inst, prec, device)
+    tol = 1e-13 if prec == "c128" else 2e-6
+    ev = band_err(reg["vx"], lds["vx"].reshape(reg["vx"].shape))
+    ee = abs(reg["ex"] - lds["ex"]) / abs(lds["ex"])
+    log(f"  V_x {ev:.2e}  E_x {ee:.2e}")
+    assert ev <= tol and ee <= tol
