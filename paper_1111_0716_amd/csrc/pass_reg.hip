@@ -26,31 +26,112 @@ template <typename T, int L>
 struct RegShape {
   using C = typename cx<T>::t;
   static constexpr int LP = L + 1;  // padded LDS row
-  static constexpr int PLANE_LDS = L * LP * static_cast<int>(sizeof(C));
-  // planes per workgroup: about 256 threads, within 150 KiB of LDS
+  // axis switches go through LDS one component (real, then imaginary) at a time
+  static constexpr int PLANE_LDS = L * LP * static_cast<int>(sizeof(T));
+  // planes per workgroup: about 256 threads, two workgroups' LDS per compute unit
   static constexpr int PL0 = (256 / L) > 0 ? (256 / L) : 1;
-  static constexpr int PL = (PL0 * PLANE_LDS <= 150 * 1024) ? PL0 : ((150 * 1024) / PLANE_LDS > 0 ? (150 * 1024) / PLANE_LDS : 1);
+  static constexpr int PL = (PL0 * PLANE_LDS <= 78 * 1024) ? PL0 : ((78 * 1024) / PLANE_LDS > 0 ? (78 * 1024) / PLANE_LDS : 1);
   static constexpr int NTP = PL * L;             // threads of the plane and accumulate passes
   static constexpr int NG = (L + PL - 1) / PL;   // plane groups
   static constexpr int LDS = PL * PLANE_LDS;
   static constexpr int NTL = 256;                // threads of the pencil pass (one line each)
   static constexpr int NLB = (L * L + NTL - 1) / NTL;  // line blocks per pair
+  // waves per SIMD each kernel is compiled for (register budget 512 / WPE):
+  // two where the line (and the accumulator) leave room for the transform
+  // without spilling, as measured on the compiled kernels
+  static constexpr int LINE_REGS = L * static_cast<int>(sizeof(C)) / 4;
+  static constexpr int WPE_PLANE = L <= 64 ? 2 : 1;
+  static constexpr int WPE_PENCIL = L <= 48 ? 2 : 1;
+  static constexpr int WPE_ACC = 2 * LINE_REGS <= 160 ? 2 : 1;
 };
+
+// Loads issued in batches of kB elements with the next batch in flight while
+// the current one is consumed: a phase costs about one memory latency, and
+// only two batches of operands are live beside the line.
+constexpr int kRegB = 8;
+
+// Compiler-only barrier: loads are not hoisted across it.
+__device__ __forceinline__ void reg_fence() { asm volatile("" ::: "memory"); }
+
+// x[j] = conj(b[j * stride]) a[j * stride], j < L
+template <typename C, int L>
+__device__ __forceinline__ void load_codensity_line(C* x, const C* __restrict__ a, const C* __restrict__ b,
+                                                    int stride) {
+  static_assert(L % 2 == 0 || L % 3 == 0, "line length");
+  constexpr int B = (L % kRegB == 0) ? kRegB : (L % 6 == 0 ? 6 : (L % 4 == 0 ? 4 : 1));
+  constexpr int NB = L / B;
+  C ab[2][B], bb[2][B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) {
+    ab[0][j] = a[j * stride];
+    bb[0][j] = b[j * stride];
+  }
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    if (n + 1 < NB) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        ab[(n + 1) & 1][j] = a[((n + 1) * B + j) * stride];
+        bb[(n + 1) & 1][j] = b[((n + 1) * B + j) * stride];
+      }
+    }
+    reg_fence();
+#pragma unroll
+    for (int j = 0; j < B; ++j) x[n * B + j] = cmulconj(bb[n & 1][j], ab[n & 1][j]);
+  }
+}
+
+// x[j] *= v[j * stride], j < L
+template <typename C, typename T, int L>
+__device__ __forceinline__ void mul_table_line(C* x, const T* __restrict__ v, size_t stride) {
+  constexpr int B = (L % kRegB == 0) ? kRegB : (L % 6 == 0 ? 6 : (L % 4 == 0 ? 4 : 1));
+  constexpr int NB = L / B;
+  T vb[2][B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) vb[0][j] = v[j * stride];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    if (n + 1 < NB) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) vb[(n + 1) & 1][j] = v[((n + 1) * B + j) * stride];
+    }
+    reg_fence();
+#pragma unroll
+    for (int j = 0; j < B; ++j) x[n * B + j] = cscale(x[n * B + j], vb[n & 1][j]);
+  }
+}
+
+// Switch a plane's axis: thread `col` holds line x[i] = P[i][col]; afterwards
+// it holds x[i] = P[col][i].  One component at a time through sp ([L][LP]
+// of T, this plane's share of LDS); every thread of the block must call it.
+template <typename C, typename T, int L>
+__device__ __forceinline__ void transpose_plane(C* x, T* sp, int col) {
+  constexpr int LP = L + 1;
+  __syncthreads();  // earlier readers of sp are done
+#pragma unroll
+  for (int i = 0; i < L; ++i) sp[i * LP + col] = x[i].x;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < L; ++i) x[i].x = sp[col * LP + i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < L; ++i) sp[i * LP + col] = x[i].y;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < L; ++i) x[i].y = sp[col * LP + i];
+}
 
 // ---------------------------------------------------------------------------
 // plane pass: rho = conj(u_m) u_n, FFT along axes 2 and 3, T[j1][c3][c2]
 // ---------------------------------------------------------------------------
 template <typename T, int L, bool EXPLICIT>
-__global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_plane_reg(int nbands, long long bs,
-                                                                    const typename cx<T>::t* __restrict__ psi, int o0,
-                                                                    int nP, const int2* __restrict__ parts,
-                                                                    const PairRef* __restrict__ pairs,
-                                                                    typename cx<T>::t* __restrict__ tbuf) {
+__global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE)) void k_plane_reg(
+    int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP,
+    const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
   extern __shared__ unsigned char smem_raw[];
-  C* s = reinterpret_cast<C*>(smem_raw);
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int j1 = blockIdx.x * Sh::PL + pl;
   const bool valid = j1 < L;
@@ -68,21 +149,14 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_plane_reg(int nbands,
   }
   C x[L];
   if (valid) {
-    const C* a = psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
-    const C* b = psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col;
-#pragma unroll
-    for (int j2 = 0; j2 < L; ++j2) x[j2] = cmulconj(b[j2 * L], a[j2 * L]);
+    load_codensity_line<C, L>(x, psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col,
+                              psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col, L);
   } else {
 #pragma unroll
     for (int j2 = 0; j2 < L; ++j2) x[j2] = C{T(0), T(0)};
   }
   reg_fft<C, L, -1>(x);  // axis 2: x[c2] at (j1, c2, j3 = col)
-  C* sp = s + pl * L * Sh::LP;
-#pragma unroll
-  for (int c2 = 0; c2 < L; ++c2) sp[c2 * Sh::LP + col] = x[c2];
-  __syncthreads();
-#pragma unroll
-  for (int j3 = 0; j3 < L; ++j3) x[j3] = sp[col * Sh::LP + j3];  // thread now holds c2 = col
+  transpose_plane<C, T, L>(x, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col);  // now c2 = col
   reg_fft<C, L, -1>(x);  // axis 3: x[c3]
   if (valid) {
     C* dst = tbuf + (static_cast<size_t>(pi) * L + j1) * LL + col;
@@ -95,7 +169,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_plane_reg(int nbands,
 // pencil pass, apply: FFT_1, x v_q/N, IFFT_1 on lines (c3, c2) of T
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_pencil_apply_reg(int nbands, int nk, int o0, int nP,
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_apply_reg(int nbands, int nk, int o0, int nP,
                                                           const int2* __restrict__ parts, const int* __restrict__ qmap,
                                                           typename cx<T>::t* __restrict__ tbuf,
                                                           const T* __restrict__ vtab) {
@@ -112,9 +186,7 @@ __global__ __launch_bounds__(256) void k_pencil_apply_reg(int nbands, int nk, in
 #pragma unroll
   for (int j1 = 0; j1 < L; ++j1) x[j1] = base[static_cast<size_t>(j1) * LL];
   reg_fft<C, L, -1>(x);
-  const T* v = vtab + static_cast<size_t>(q) * LL * L + l;
-#pragma unroll
-  for (int c1 = 0; c1 < L; ++c1) x[c1] = cscale(x[c1], v[static_cast<size_t>(c1) * LL]);
+  mul_table_line<C, T, L>(x, vtab + static_cast<size_t>(q) * LL * L + l, LL);
   reg_fft<C, L, +1>(x);
 #pragma unroll
   for (int j1 = 0; j1 < L; ++j1) base[static_cast<size_t>(j1) * LL] = x[j1];
@@ -124,7 +196,7 @@ __global__ __launch_bounds__(256) void k_pencil_apply_reg(int nbands, int nk, in
 // pencil pass, energy: FFT_1 and sum v_q/N |P|^2 in FP64 per line block
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_pencil_energy_reg(const PairRef* __restrict__ pairs,
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_energy_reg(const PairRef* __restrict__ pairs,
                                                            const typename cx<T>::t* __restrict__ tbuf,
                                                            const T* __restrict__ vtab, double* __restrict__ epart) {
   using C = typename cx<T>::t;
@@ -159,25 +231,23 @@ __global__ __launch_bounds__(256) void k_pencil_energy_reg(const PairRef* __rest
 // accumulate pass: per (output, plane group), every partner of the batch
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_acc_reg(int nbands, long long bs, int o0, int nP,
-                                                                  const int2* __restrict__ parts,
-                                                                  const typename cx<T>::t* __restrict__ tbuf,
-                                                                  const typename cx<T>::t* __restrict__ psi,
-                                                                  const double* __restrict__ occ,
-                                                                  const double* __restrict__ kw,
-                                                                  typename cx<T>::t* __restrict__ out, int first,
-                                                                  const double* __restrict__ gscale, double hscale,
-                                                                  int backward) {
+__global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) void k_acc_reg(
+    int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
+    const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
+    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    const double* __restrict__ gscale, double hscale, int backward) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
+  constexpr int B = (L % kRegB == 0) ? kRegB : (L % 6 == 0 ? 6 : (L % 4 == 0 ? 4 : 1));
+  constexpr int NB = L / B;
   extern __shared__ unsigned char smem_raw[];
-  C* s = reinterpret_cast<C*>(smem_raw);
+  T* sp = reinterpret_cast<T*>(smem_raw);
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int j1 = blockIdx.x * Sh::PL + pl;
   const bool valid = j1 < L;
   const int o = blockIdx.y;
-  C* sp = s + pl * L * Sh::LP;
+  sp += pl * L * Sh::LP;
   C acc[L];
 #pragma unroll
   for (int j2 = 0; j2 < L; ++j2) acc[j2] = C{T(0), T(0)};
@@ -192,22 +262,28 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP)) void k_acc_reg(int nbands, l
 #pragma unroll
       for (int c3 = 0; c3 < L; ++c3) x[c3] = C{T(0), T(0)};
     }
-    reg_fft<C, L, +1>(x);  // inverse axis 3: x[j3] at (j1, c2 = col)
-    __syncthreads();       // the previous partner's columns have been read
-#pragma unroll
-    for (int j3 = 0; j3 < L; ++j3) sp[j3 * Sh::LP + col] = x[j3];
-    __syncthreads();
-#pragma unroll
-    for (int c2 = 0; c2 < L; ++c2) x[c2] = sp[col * Sh::LP + c2];  // column (j1, j3 = col)
-    reg_fft<C, L, +1>(x);  // inverse axis 2: x[j2]
+    reg_fft<C, L, +1>(x);                   // inverse axis 3: x[j3] at (j1, c2 = col)
+    transpose_plane<C, T, L>(x, sp, col);   // column (j1, j3 = col)
+    reg_fft<C, L, +1>(x);                   // inverse axis 2: x[j2]
     if (valid) {
       const T coef = static_cast<T>(-kw[r.x] * occ[r.x * nbands + r.y]);
       const C* um = psi + static_cast<size_t>(r.x * nbands + r.y) * bs + static_cast<size_t>(j1) * LL + col;
+      C mb[2][B];
 #pragma unroll
-      for (int j2 = 0; j2 < L; ++j2) {
-        const C w = cmul(um[j2 * L], x[j2]);
-        acc[j2].x += coef * w.x;
-        acc[j2].y += coef * w.y;
+      for (int j = 0; j < B; ++j) mb[0][j] = um[j * L];
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        if (n + 1 < NB) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = um[((n + 1) * B + j) * L];
+        }
+        reg_fence();
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const C w = cmul(mb[n & 1][j], x[n * B + j]);
+          acc[n * B + j].x += coef * w.x;
+          acc[n * B + j].y += coef * w.y;
+        }
       }
     }
   }

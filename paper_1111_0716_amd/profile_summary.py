@@ -28,10 +28,11 @@ import shlex
 import sys
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-# source files of each kernel kind (the .hip file and the headers it includes)
+# source files of each kernel kind's device code (the .hip file and the
+# headers its kernels use)
 KIND_SOURCES = {
-    "fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "energy_fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp"],
+    "energy_fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp"],
     "plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
     "pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
     "accumulate": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
