@@ -1,6 +1,6 @@
 // Three-pass kernels with register-line FFTs for cubic grids L^3 that do not
-// take the whole-pair kernels (L in {24, 32, 40, 48, 64, 72} FP32, L in
-// {24, 32} FP64; larger FP64 lines would spill).  Same passes and batching as the LDS-Stockham kernels (paper,
+// take the whole-pair kernels, L in {24, 32, 40, 48, 64, 72}: a line per lane
+// (FP32 L <= 48, FP64 L <= 32) or a line per lane pair (larger L).  Same passes and batching as the LDS-Stockham kernels (paper,
 // "Our Implementation": the band-pair loop on the GPU; NSIM-like blocks of
 // outputs x partners), but every 1-D transform runs in one thread's registers
 // on a whole line (reg_fft.hpp), a plane switches axes through one padded LDS
@@ -303,15 +303,273 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
 }
 
 // ---------------------------------------------------------------------------
+// two-lane lines (L >= 64 FP32, L >= 40 FP64): each line lives in a lane pair
+// ---------------------------------------------------------------------------
+// The lanes 2i and 2i+1 share a line; lane h holds the samples 2m + h, or
+// after a forward transform the half h of the spectrum (split_fft_fwd /
+// split_fft_inv in reg_fft.hpp).  Registers per lane halve, so these kernels
+// keep two or more waves per SIMD where a whole line per lane could not.
+template <typename T, int L>
+struct SplitShape {
+  using C = typename cx<T>::t;
+  static constexpr int LH = L / 2;
+  static constexpr int LP = L + 1;
+  static constexpr int PLANE_LDS = L * LP * static_cast<int>(sizeof(T));
+  static constexpr int TPP = 2 * L;  // threads per plane
+  static constexpr int HALF_REGS = LH * static_cast<int>(sizeof(C)) / 4;
+  // planes per workgroup: up to 320 threads, but at most four waves (a whole
+  // SIMD's registers per wave) when the accumulator and the half line need
+  // more than 160 registers
+  static constexpr int TMAX = 2 * HALF_REGS > 160 ? 256 : 320;
+  static constexpr int PL = (TMAX / TPP) > 0 ? (TMAX / TPP) : 1;
+  static constexpr int NTP = PL * TPP;
+  static constexpr int NG = (L + PL - 1) / PL;
+  static constexpr int LDS = PL * PLANE_LDS;
+  static constexpr int LPB = 128;  // lines per pencil block
+  static constexpr int NLB = (L * L + LPB - 1) / LPB;
+  static constexpr int WPE_LINE = HALF_REGS <= 64 ? 3 : (HALF_REGS <= 72 ? 2 : 1);
+  static constexpr int WPE_ACC = 2 * HALF_REGS <= 144 ? 2 : 1;
+};
+
+// Switch a plane's axis for split lines.  EO_IN: the lane holds the samples
+// i = 2m + h of line `col` and receives the half i = h L/2 + k of line `col`
+// of the other axis; otherwise the reverse.  Component-wise through sp.
+template <typename C, typename T, int L, bool EO_IN>
+__device__ __forceinline__ void transpose_split(C* y, T* sp, int col, int h) {
+  constexpr int LH = L / 2, LP = L + 1;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LH; ++k) sp[(EO_IN ? 2 * k + h : h * LH + k) * LP + col] = y[k].x;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LH; ++k) y[k].x = sp[col * LP + (EO_IN ? h * LH + k : 2 * k + h)];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LH; ++k) sp[(EO_IN ? 2 * k + h : h * LH + k) * LP + col] = y[k].y;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < LH; ++k) y[k].y = sp[col * LP + (EO_IN ? h * LH + k : 2 * k + h)];
+}
+
+template <typename T, int L, bool EXPLICIT>
+__global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LINE)) void k_plane_split(
+    int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP,
+    const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
+  using C = typename cx<T>::t;
+  using Sh = SplitShape<T, L>;
+  constexpr int LL = L * L, LH = Sh::LH;
+  extern __shared__ unsigned char smem_raw[];
+  const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
+  const int j1 = blockIdx.x * Sh::PL + pl;
+  const bool valid = j1 < L;
+  const int pi = blockIdx.y;
+  int okn, pkm;
+  if (EXPLICIT) {
+    const PairRef pr = pairs[pi];
+    okn = pr.k * nbands + pr.n;
+    pkm = pr.kp * nbands + pr.m;
+  } else {
+    const int o = pi / nP, p = pi - o * nP;
+    okn = o0 + o;
+    const int2 r = parts[p];
+    pkm = r.x * nbands + r.y;
+  }
+  C y[LH];
+  if (valid) {
+    const size_t off = static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * L + col;  // j2 = 2m + h
+    load_codensity_line<C, LH>(y, psi + static_cast<size_t>(okn) * bs + off, psi + static_cast<size_t>(pkm) * bs + off,
+                               2 * L);
+  } else {
+#pragma unroll
+    for (int m = 0; m < LH; ++m) y[m] = C{T(0), T(0)};
+  }
+  split_fft_fwd<C, L>(y, h);  // axis 2: y[k] at c2 = h L/2 + k, j3 = col
+  transpose_split<C, T, L, false>(y, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col, h);  // c2 = col
+  split_fft_fwd<C, L>(y, h);  // axis 3: y[k] at c3 = h L/2 + k
+  if (valid) {
+    C* dst = tbuf + (static_cast<size_t>(pi) * L + j1) * LL + static_cast<size_t>(h) * LH * L + col;
+#pragma unroll
+    for (int k = 0; k < LH; ++k) dst[k * L] = y[k];
+  }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_apply_split(
+    int nbands, int nk, int o0, int nP, const int2* __restrict__ parts, const int* __restrict__ qmap,
+    typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab) {
+  using C = typename cx<T>::t;
+  using Sh = SplitShape<T, L>;
+  constexpr int LL = L * L, LH = Sh::LH;
+  const int h = threadIdx.x & 1;
+  const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
+  const int pi = blockIdx.y;
+  if (l >= LL) return;  // uniform over the pair; no barrier in this kernel
+  const int o = pi / nP, p = pi - o * nP;
+  const int q = qmap[((o0 + o) / nbands) * nk + parts[p].x];
+  C* base = tbuf + static_cast<size_t>(pi) * LL * L + static_cast<size_t>(h) * LL + l;
+  C y[LH];
+#pragma unroll
+  for (int m = 0; m < LH; ++m) y[m] = base[static_cast<size_t>(2 * m) * LL];  // j1 = 2m + h
+  split_fft_fwd<C, L>(y, h);  // y[k] at c1 = h L/2 + k
+  mul_table_line<C, T, LH>(y, vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l, LL);
+  split_fft_inv<C, L>(y, h);
+#pragma unroll
+  for (int m = 0; m < LH; ++m) base[static_cast<size_t>(2 * m) * LL] = y[m];
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_energy_split(
+    const PairRef* __restrict__ pairs, const typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab,
+    double* __restrict__ epart) {
+  using C = typename cx<T>::t;
+  using Sh = SplitShape<T, L>;
+  constexpr int LL = L * L, LH = Sh::LH;
+  __shared__ double red[4];
+  const int h = threadIdx.x & 1;
+  const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);
+  const int pi = blockIdx.y;
+  double e = 0.0;
+  if (l < LL) {
+    const int q = pairs[pi].q;
+    const C* base = tbuf + static_cast<size_t>(pi) * LL * L + static_cast<size_t>(h) * LL + l;
+    C y[LH];
+#pragma unroll
+    for (int m = 0; m < LH; ++m) y[m] = base[static_cast<size_t>(2 * m) * LL];
+    split_fft_fwd<C, L>(y, h);
+    const T* v = vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l;
+#pragma unroll
+    for (int k = 0; k < LH; ++k) {
+      const double px = static_cast<double>(y[k].x), py = static_cast<double>(y[k].y);
+      e += static_cast<double>(v[static_cast<size_t>(k) * LL]) * (px * px + py * py);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * Sh::NLB + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC)) void k_acc_split(
+    int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
+    const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
+    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    const double* __restrict__ gscale, double hscale, int backward) {
+  using C = typename cx<T>::t;
+  using Sh = SplitShape<T, L>;
+  constexpr int LL = L * L, LH = Sh::LH;
+  constexpr int B = (LH % kRegB == 0) ? kRegB : (LH % 6 == 0 ? 6 : (LH % 4 == 0 ? 4 : 1));
+  constexpr int NB = LH / B;
+  extern __shared__ unsigned char smem_raw[];
+  const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
+  const int j1 = blockIdx.x * Sh::PL + pl;
+  const bool valid = j1 < L;
+  const int o = blockIdx.y;
+  T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
+  // element (j1, 2m + h, col) of a grid: the lane's samples along axis 2
+  const size_t eo = static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * L + col;
+  C acc[LH];
+#pragma unroll
+  for (int m = 0; m < LH; ++m) acc[m] = C{T(0), T(0)};
+  for (int p = 0; p < nP; ++p) {
+    const int2 r = parts[p];
+    C y[LH];
+    if (valid) {
+      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * L + static_cast<size_t>(j1) * LL +
+                     static_cast<size_t>(h) * LH * L + col;
+#pragma unroll
+      for (int k = 0; k < LH; ++k) y[k] = src[k * L];  // row (j1, c2 = col), c3 = h L/2 + k
+    } else {
+#pragma unroll
+      for (int k = 0; k < LH; ++k) y[k] = C{T(0), T(0)};
+    }
+    split_fft_inv<C, L>(y, h);                      // inverse axis 3: y[m] at j3 = 2m + h
+    transpose_split<C, T, L, true>(y, sp, col, h);  // column j3 = col, c2 = h L/2 + k
+    split_fft_inv<C, L>(y, h);                      // inverse axis 2: y[m] at j2 = 2m + h
+    if (valid) {
+      const T coef = static_cast<T>(-kw[r.x] * occ[r.x * nbands + r.y]);
+      const C* um = psi + static_cast<size_t>(r.x * nbands + r.y) * bs + eo;
+      C mb[2][B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) mb[0][j] = um[j * 2 * L];
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        if (n + 1 < NB) {
+#pragma unroll
+          for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = um[((n + 1) * B + j) * 2 * L];
+        }
+        reg_fence();
+#pragma unroll
+        for (int j = 0; j < B; ++j) {
+          const C w = cmul(mb[n & 1][j], y[n * B + j]);
+          acc[n * B + j].x += coef * w.x;
+          acc[n * B + j].y += coef * w.y;
+        }
+      }
+    }
+  }
+  if (!valid) return;  // no barrier after this point
+  const int okn = o0 + o;
+  double f = hscale;
+  if (gscale) f *= gscale[0];
+  if (backward) f *= kw[okn / nbands] * occ[okn];
+  const T ft = static_cast<T>(f);
+  C* dst = out + static_cast<size_t>(okn) * bs + eo;
+#pragma unroll
+  for (int m = 0; m < LH; ++m) {
+    C v = cscale(acc[m], ft);
+    if (!first) v = cadd(dst[m * 2 * L], v);
+    dst[m * 2 * L] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Every variant reads and writes the pair buffer in the same layout, so each
+// pass picks its own: a line per lane where that fits the registers without
+// spilling, a line per lane pair otherwise, and by measurement where both fit
+// (FP32 64^3: two-lane pencil and accumulate; FP32 72^3: two-lane pencil).
+template <typename T, int L>
+struct RegPolicy {
+  static constexpr bool FP32 = sizeof(T) == 4;
+  static constexpr bool SPLIT_PLANE = !FP32 && L >= 40;
+  static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 40;
+  static constexpr bool SPLIT_ACC = FP32 ? L == 64 : L >= 40;
+  static constexpr int PLANE_NG = SPLIT_PLANE ? SplitShape<T, L>::NG : RegShape<T, L>::NG;
+  static constexpr int PLANE_NT = SPLIT_PLANE ? SplitShape<T, L>::NTP : RegShape<T, L>::NTP;
+  static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
+  static constexpr int ACC_NG = SPLIT_ACC ? SplitShape<T, L>::NG : RegShape<T, L>::NG;
+  static constexpr int ACC_NT = SPLIT_ACC ? SplitShape<T, L>::NTP : RegShape<T, L>::NTP;
+  static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
+  static constexpr int NLB = SPLIT_PENCIL ? SplitShape<T, L>::NLB : RegShape<T, L>::NLB;
+  static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;
+};
+
 namespace {
+
+template <typename T, int L, bool EXPLICIT>
+void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void* psi, const int2* parts,
+                  const PairRef* pairs, typename cx<T>::t* tbuf) {
+  using C = typename cx<T>::t;
+  using Po = RegPolicy<T, L>;
+  const long long bs = static_cast<long long>(in.band_stride);
+  const int o0 = EXPLICIT ? 0 : b.o0, nP = EXPLICIT ? 1 : b.nP;
+  if constexpr (Po::SPLIT_PLANE) {
+    hipLaunchKernelGGL((k_plane_split<T, L, EXPLICIT>), dim3(Po::PLANE_NG, b.npairs), dim3(Po::PLANE_NT),
+                       Po::PLANE_LDS, p.stream, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
+  } else {
+    hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), dim3(Po::PLANE_NG, b.npairs), dim3(Po::PLANE_NT),
+                       Po::PLANE_LDS, p.stream, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
+  }
+}
 
 template <typename T, int L>
 hipError_t reg_apply_L(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                        const double* gscale, double hscale, bool backward) {
   using C = typename cx<T>::t;
-  using Sh = RegShape<T, L>;
+  using Po = RegPolicy<T, L>;
   const Instance& in = p.inst[b.inst];
   const long long bs = static_cast<long long>(in.band_stride);
   const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
@@ -320,18 +578,27 @@ hipError_t reg_apply_L(const Plan& p, const Batch& b, const void* psi, const dou
   const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
   C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
   p.prof.begin(FOCK_K_PLANE, p.stream);
-  hipLaunchKernelGGL((k_plane_reg<T, L, false>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
-                     in.nbands, bs, static_cast<const C*>(psi), b.o0, b.nP, parts,
-                     static_cast<const PairRef*>(nullptr), tbuf);
+  launch_plane<T, L, false>(p, b, in, psi, parts, nullptr, tbuf);
   p.prof.end(FOCK_K_PLANE, p.stream);
   p.prof.begin(FOCK_K_PENCIL, p.stream);
-  hipLaunchKernelGGL((k_pencil_apply_reg<T, L>), dim3(Sh::NLB, b.npairs), dim3(256), 0, p.stream, in.nbands, in.nk,
-                     b.o0, b.nP, parts, qmap, tbuf, vtab);
+  if constexpr (Po::SPLIT_PENCIL) {
+    hipLaunchKernelGGL((k_pencil_apply_split<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, in.nbands,
+                       in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+  } else {
+    hipLaunchKernelGGL((k_pencil_apply_reg<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, in.nbands,
+                       in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+  }
   p.prof.end(FOCK_K_PENCIL, p.stream);
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
-  hipLaunchKernelGGL((k_acc_reg<T, L>), dim3(Sh::NG, b.nO), dim3(Sh::NTP), Sh::LDS, p.stream, in.nbands, bs, b.o0,
-                     b.nP, parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ, kw,
-                     static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
+  if constexpr (Po::SPLIT_ACC) {
+    hipLaunchKernelGGL((k_acc_split<T, L>), dim3(Po::ACC_NG, b.nO), dim3(Po::ACC_NT), Po::ACC_LDS, p.stream,
+                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ,
+                       kw, static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL((k_acc_reg<T, L>), dim3(Po::ACC_NG, b.nO), dim3(Po::ACC_NT), Po::ACC_LDS, p.stream,
+                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ,
+                       kw, static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
+  }
   p.prof.end(FOCK_K_ACCUMULATE, p.stream);
   return hipGetLastError();
 }
@@ -339,73 +606,75 @@ hipError_t reg_apply_L(const Plan& p, const Batch& b, const void* psi, const dou
 template <typename T, int L>
 hipError_t reg_energy_L(const Plan& p, const Batch& b, const void* psi, const double* occ) {
   using C = typename cx<T>::t;
-  using Sh = RegShape<T, L>;
+  using Po = RegPolicy<T, L>;
   const Instance& in = p.inst[b.inst];
   const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
   const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
   C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
   double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
   p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
-  hipLaunchKernelGGL((k_plane_reg<T, L, true>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
-                     in.nbands, static_cast<long long>(in.band_stride), static_cast<const C*>(psi), 0, 1,
-                     static_cast<const int2*>(nullptr), pairs, tbuf);
+  launch_plane<T, L, true>(p, b, in, psi, nullptr, pairs, tbuf);
   p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
   p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
-  hipLaunchKernelGGL((k_pencil_energy_reg<T, L>), dim3(Sh::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
-                     static_cast<const C*>(tbuf), vtab, epart);
+  if constexpr (Po::SPLIT_PENCIL) {
+    hipLaunchKernelGGL((k_pencil_energy_split<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
+                       static_cast<const C*>(tbuf), vtab, epart);
+  } else {
+    hipLaunchKernelGGL((k_pencil_energy_reg<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
+                       static_cast<const C*>(tbuf), vtab, epart);
+  }
   p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
-  return launch_energy_reduce(p, b, occ, Sh::NLB);
+  return launch_energy_reduce(p, b, occ, Po::NLB);
 }
 
-// the lengths with register-line kernels, per precision
-#define FOCK_REG_F32(X) X(24) X(32) X(40) X(48) X(64) X(72)
-#define FOCK_REG_F64(X) X(24) X(32)
+template <typename T, int L>
+void reg_lds_attr(int lim) {
+  using Po = RegPolicy<T, L>;
+  const void* fs[3];
+  if constexpr (Po::SPLIT_PLANE) {
+    fs[0] = reinterpret_cast<const void*>(&k_plane_split<T, L, false>);
+    fs[1] = reinterpret_cast<const void*>(&k_plane_split<T, L, true>);
+  } else {
+    fs[0] = reinterpret_cast<const void*>(&k_plane_reg<T, L, false>);
+    fs[1] = reinterpret_cast<const void*>(&k_plane_reg<T, L, true>);
+  }
+  if constexpr (Po::SPLIT_ACC)
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<T, L>);
+  else
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L>);
+  for (const void* f : fs)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+}
+
+// the cubic lengths with register-line kernels
+#define FOCK_REG_L(X) X(24) X(32) X(40) X(48) X(64) X(72)
 
 template <typename T>
 hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                        const double* gscale, double hscale, bool backward) {
-  const int L = p.inst[b.inst].grid[0];
 #define CASE(N) \
   case N: return reg_apply_L<T, N>(p, b, psi, occ, out, gscale, hscale, backward);
-  if constexpr (sizeof(T) == 4) {
-    switch (L) { FOCK_REG_F32(CASE) default: break; }
-  } else {
-    switch (L) { FOCK_REG_F64(CASE) default: break; }
-  }
+  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
 #undef CASE
   return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
-  const int L = p.inst[b.inst].grid[0];
 #define CASE(N) \
   case N: return reg_energy_L<T, N>(p, b, psi, occ);
-  if constexpr (sizeof(T) == 4) {
-    switch (L) { FOCK_REG_F32(CASE) default: break; }
-  } else {
-    switch (L) { FOCK_REG_F64(CASE) default: break; }
-  }
+  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
 #undef CASE
   return hipErrorInvalidValue;
-}
-
-template <typename T, int L>
-void reg_lds_attr(int lim) {
-  const void* fs[] = {reinterpret_cast<const void*>(&k_plane_reg<T, L, false>),
-                      reinterpret_cast<const void*>(&k_plane_reg<T, L, true>),
-                      reinterpret_cast<const void*>(&k_acc_reg<T, L>)};
-  for (const void* f : fs)
-    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
 
 }  // namespace
 
 bool reg_supported(fock_precision prec, const int grid[3]) {
+  (void)prec;
   if (grid[0] != grid[1] || grid[0] != grid[2]) return false;
   switch (grid[0]) {
-    case 24: case 32: return true;
-    case 40: case 48: case 64: case 72: return prec == FOCK_C64;
+    case 24: case 32: case 40: case 48: case 64: case 72: return true;
     default: return false;
   }
 }
@@ -413,31 +682,16 @@ bool reg_supported(fock_precision prec, const int grid[3]) {
 size_t reg_lds_bytes(fock_precision prec, int L) {
   size_t r = 0;
 #define CASE(N) \
-  case N: r = RegShape<float, N>::LDS; break;
-  if (prec == FOCK_C64) {
-    switch (L) { FOCK_REG_F32(CASE) default: break; }
-  }
-#undef CASE
-#define CASE(N) \
-  case N: r = RegShape<double, N>::LDS; break;
-  if (prec == FOCK_C128) {
-    switch (L) { FOCK_REG_F64(CASE) default: break; }
-  }
+  case N: r = prec == FOCK_C64 ? RegPolicy<float, N>::LDS : RegPolicy<double, N>::LDS; break;
+  switch (L) { FOCK_REG_L(CASE) default: break; }
 #undef CASE
   return r;
 }
 
-int reg_energy_slots(fock_precision prec, int L) {
-  (void)prec;
-  return (L * L + 255) / 256;
-}
-
 void prepare_reg_kernels(fock_precision prec, int lim) {
-#define CASE(N) reg_lds_attr<float, N>(lim);
-  if (prec == FOCK_C64) { FOCK_REG_F32(CASE) }
-#undef CASE
-#define CASE(N) reg_lds_attr<double, N>(lim);
-  if (prec == FOCK_C128) { FOCK_REG_F64(CASE) }
+#define CASE(N) \
+  if (prec == FOCK_C64) reg_lds_attr<float, N>(lim); else reg_lds_attr<double, N>(lim);
+  FOCK_REG_L(CASE)
 #undef CASE
 }
 

@@ -77,6 +77,12 @@ CASES = [
     ((32, 32, 32), (1, 2, 1), 2, True, "c128"),
     ((40, 40, 40), (1, 1, 1), 2, False, "c64"),
     ((48, 48, 48), (2, 1, 1), 2, True, "c64"),
+    # lines shared by a lane pair (FP64 40^3 and up, FP32 64^3 and up)
+    ((40, 40, 40), (1, 2, 1), 2, False, "c128"),
+    ((48, 48, 48), (1, 1, 1), 2, True, "c128"),
+    ((64, 64, 64), (1, 1, 1), 1, False, "c128"),
+    ((72, 72, 72), (1, 1, 1), 1, True, "c128"),
+    ((64, 64, 64), (2, 1, 1), 1, True, "c64"),
     # whole-pair path (cubic grids that fit one compute unit)
     ((32, 32, 32), (1, 1, 1), 3, False, "c64"),
     ((32, 32, 32), (2, 1, 1), 2, True, "c64"),
@@ -140,7 +146,8 @@ def test_fp64_results_are_bitwise_reproducible(device):
 
 
 @pytest.mark.parametrize("grid,prec", [((10, 12, 9), "c128"), ((10, 12, 9), "c64"), ((16, 16, 16), "c64"),
-                                       ((24, 24, 24), "c64"), ((16, 16, 16), "c128")])
+                                       ((24, 24, 24), "c64"), ((16, 16, 16), "c128"), ((32, 32, 32), "c128"),
+                                       ((64, 64, 64), "c64"), ((40, 40, 40), "c128")])
 def test_backward_matches_oracle_gradient(grid, prec, device):
     import torch
 
@@ -247,7 +254,8 @@ def test_whole_pair_explicit_k_pairs(kp, device):
 
 
 @pytest.mark.parametrize("grid,prec", [((32, 32, 32), "c128"), ((24, 24, 24), "c128"), ((48, 48, 48), "c64"),
-                                       ((64, 64, 64), "c64")])
+                                       ((64, 64, 64), "c64"), ((72, 72, 72), "c64"), ((40, 40, 40), "c128"),
+                                       ((64, 64, 64), "c128")])
 def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
     """The register-line three-pass kernels and the LDS-Stockham three-pass
     kernels compute the same operator and energy (FP64: to rounding)."""
