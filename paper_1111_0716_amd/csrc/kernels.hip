@@ -189,11 +189,19 @@ __global__ __launch_bounds__(kBlock) void k_inv_plane_acc(Geo g, int o0, int nP,
     fft_lines_call<C, +1, true>(s, g.n3, g.n2, g.n3, 1, tw);   // inverse axis 3
     const T coef = static_cast<T>(-kw[r.x] * occ[r.x * g.nbands + r.y]);
     const C* um = psi + static_cast<size_t>(r.x * g.nbands + r.y) * g.bs + static_cast<size_t>(j1) * plane;
+    // elements past the plane load element 0 (in bounds) and are not used:
+    // the loads stay unconditional and overlap
+    C u[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = threadIdx.x + i * kBlock;
+      u[i] = um[e < plane ? e : 0];
+    }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = threadIdx.x + i * kBlock;
       if (e < plane) {
-        const C w = cmul(um[e], s[e]);
+        const C w = cmul(u[i], s[e]);
         acc[i].x += coef * w.x;
         acc[i].y += coef * w.y;
       }
@@ -209,14 +217,16 @@ __global__ __launch_bounds__(kBlock) void k_inv_plane_acc(Geo g, int o0, int nP,
   }
   const T ft = static_cast<T>(f);
   C* dst = out + static_cast<size_t>(okn) * g.bs + static_cast<size_t>(j1) * plane;
+  C old[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int e = threadIdx.x + i * kBlock;
-    if (e < plane) {
-      C v = cscale(acc[i], ft);
-      if (!first) v = cadd(dst[e], v);
-      dst[e] = v;
-    }
+    old[i] = first ? C{T(0), T(0)} : dst[e < plane ? e : 0];  // all loads before the first store
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = threadIdx.x + i * kBlock;
+    if (e < plane) dst[e] = cadd(old[i], cscale(acc[i], ft));
   }
 }
 

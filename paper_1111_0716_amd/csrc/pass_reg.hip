@@ -22,6 +22,11 @@
 
 namespace fock {
 
+// Loads issued in batches with the next batch in flight while the current one
+// is consumed: only two batches of operands are live beside the line, and a
+// phase costs (elements / batch) - 1 memory latencies at most.
+constexpr int kRegB = 8;
+
 template <typename T, int L>
 struct RegShape {
   using C = typename cx<T>::t;
@@ -43,22 +48,27 @@ struct RegShape {
   static constexpr int WPE_PLANE = L <= 64 ? 2 : 1;
   static constexpr int WPE_PENCIL = L <= 48 ? 2 : 1;
   static constexpr int WPE_ACC = 2 * LINE_REGS <= 160 ? 2 : 1;
+  // operand batches: larger where the kernel has a whole SIMD's registers
+  static constexpr int PLANE_B = WPE_PLANE == 1 ? 24 : kRegB;
+  static constexpr int ACC_B = (WPE_ACC == 1 && sizeof(T) == 4) ? 16 : kRegB;
 };
 
-// Loads issued in batches of kB elements with the next batch in flight while
-// the current one is consumed: a phase costs about one memory latency, and
-// only two batches of operands are live beside the line.
-constexpr int kRegB = 8;
 
 // Compiler-only barrier: loads are not hoisted across it.
 __device__ __forceinline__ void reg_fence() { asm volatile("" ::: "memory"); }
 
-// x[j] = conj(b[j * stride]) a[j * stride], j < L
-template <typename C, int L>
+// the largest batch size <= want that divides L
+__host__ __device__ constexpr int batch_of(int L, int want) {
+  int b = want < L ? want : L;
+  while (L % b != 0) --b;
+  return b;
+}
+
+// x[j] = conj(b[j * stride]) a[j * stride], j < L, in batches of BW
+template <typename C, int L, int BW = kRegB>
 __device__ __forceinline__ void load_codensity_line(C* x, const C* __restrict__ a, const C* __restrict__ b,
                                                     int stride) {
-  static_assert(L % 2 == 0 || L % 3 == 0, "line length");
-  constexpr int B = (L % kRegB == 0) ? kRegB : (L % 6 == 0 ? 6 : (L % 4 == 0 ? 4 : 1));
+  constexpr int B = batch_of(L, BW);
   constexpr int NB = L / B;
   C ab[2][B], bb[2][B];
 #pragma unroll
@@ -84,7 +94,7 @@ __device__ __forceinline__ void load_codensity_line(C* x, const C* __restrict__ 
 // x[j] *= v[j * stride], j < L
 template <typename C, typename T, int L>
 __device__ __forceinline__ void mul_table_line(C* x, const T* __restrict__ v, size_t stride) {
-  constexpr int B = (L % kRegB == 0) ? kRegB : (L % 6 == 0 ? 6 : (L % 4 == 0 ? 4 : 1));
+  constexpr int B = batch_of(L, kRegB);
   constexpr int NB = L / B;
   T vb[2][B];
 #pragma unroll
@@ -149,8 +159,8 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE))
   }
   C x[L];
   if (valid) {
-    load_codensity_line<C, L>(x, psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col,
-                              psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col, L);
+    load_codensity_line<C, L, Sh::PLANE_B>(x, psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col,
+                                           psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col, L);
   } else {
 #pragma unroll
     for (int j2 = 0; j2 < L; ++j2) x[j2] = C{T(0), T(0)};
@@ -239,7 +249,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
-  constexpr int B = (L % kRegB == 0) ? kRegB : (L % 6 == 0 ? 6 : (L % 4 == 0 ? 4 : 1));
+  constexpr int B = batch_of(L, Sh::ACC_B);
   constexpr int NB = L / B;
   extern __shared__ unsigned char smem_raw[];
   T* sp = reinterpret_cast<T*>(smem_raw);
@@ -294,11 +304,17 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   if (backward) f *= kw[okn / nbands] * occ[okn];
   const T ft = static_cast<T>(f);
   C* dst = out + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
+  if (!first) {
+    // every earlier value is loaded before the first store, so the loads
+    // overlap instead of waiting one by one behind the stores
+    C old[L];
 #pragma unroll
-  for (int j2 = 0; j2 < L; ++j2) {
-    C v = cscale(acc[j2], ft);
-    if (!first) v = cadd(dst[j2 * L], v);
-    dst[j2 * L] = v;
+    for (int j2 = 0; j2 < L; ++j2) old[j2] = dst[j2 * L];
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cadd(old[j2], cscale(acc[j2], ft));
+  } else {
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cscale(acc[j2], ft);
   }
 }
 
@@ -459,7 +475,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
   constexpr int LL = L * L, LH = Sh::LH;
-  constexpr int B = (LH % kRegB == 0) ? kRegB : (LH % 6 == 0 ? 6 : (LH % 4 == 0 ? 4 : 1));
+  constexpr int B = batch_of(LH, Sh::WPE_ACC == 1 ? 16 : kRegB);
   constexpr int NB = LH / B;
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
@@ -516,11 +532,15 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   if (backward) f *= kw[okn / nbands] * occ[okn];
   const T ft = static_cast<T>(f);
   C* dst = out + static_cast<size_t>(okn) * bs + eo;
+  if (!first) {
+    C old[LH];  // loaded before the first store (see k_acc_reg)
 #pragma unroll
-  for (int m = 0; m < LH; ++m) {
-    C v = cscale(acc[m], ft);
-    if (!first) v = cadd(dst[m * 2 * L], v);
-    dst[m * 2 * L] = v;
+    for (int m = 0; m < LH; ++m) old[m] = dst[m * 2 * L];
+#pragma unroll
+    for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cadd(old[m], cscale(acc[m], ft));
+  } else {
+#pragma unroll
+    for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cscale(acc[m], ft);
   }
 }
 
