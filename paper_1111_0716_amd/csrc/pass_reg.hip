@@ -19,6 +19,7 @@
 #include "fft_lds.hpp"
 #include "fock_internal.hpp"
 #include "reg_fft.hpp"
+#include "split_fft.hpp"
 
 namespace fock {
 

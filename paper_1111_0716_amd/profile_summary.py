@@ -33,11 +33,11 @@ CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 KIND_SOURCES = {
     "fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp"],
     "energy_fused": ["pair_fused.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp"],
-    "plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "accumulate": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "energy_plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
-    "energy_pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "split_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "split_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "accumulate": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "split_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "energy_plane": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "split_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
+    "energy_pencil": ["kernels.hip", "pass_reg.hip", "reg_fft.hpp", "split_fft.hpp", "fft_lds.hpp", "twiddle_ce.hpp", "fock_internal.hpp"],
     "overlap": ["overlap_mfma.hip", "fft_lds.hpp", "fock_internal.hpp"],
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
