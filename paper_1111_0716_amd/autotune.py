@@ -5,7 +5,7 @@ per-kernel events and keeps the fastest, searching one knob at a time:
 
   whole-pair path   fused_split in {1, 2, 3, 4}       (partner slices per output)
   three-pass path   acc_workgroups in {512 .. 8192}    (output block size)
-                    tbuf_mb in {256, 1024, 4096}       (pairs per batch)
+                    tbuf_mb in {1024, 4096, 16384}     (pairs per batch)
 
 Only knobs of the paths the plan actually uses are searched (read from the
 kernels a default apply launches).  Results are cached as JSON keyed by the
@@ -24,7 +24,7 @@ from . import fock
 KNOBS = ("acc_workgroups", "tbuf_mb", "fused_split", "no_fused")
 FUSED_SPLITS = (1, 2, 3, 4)
 ACC_WORKGROUPS = (512, 1024, 2048, 4096, 8192)
-TBUF_MB = (256, 1024, 4096)
+TBUF_MB = (1024, 4096, 16384)
 
 
 def cache_path():

@@ -221,7 +221,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   }
 
   // ---- batch shapes ----
-  const size_t tbuf_target = (tn.tbuf_mb > 0 ? static_cast<size_t>(tn.tbuf_mb) : env_mb("FOCK_TBUF_MB", 1024)) << 20;
+  const size_t tbuf_target = (tn.tbuf_mb > 0 ? static_cast<size_t>(tn.tbuf_mb) : env_mb("FOCK_TBUF_MB", 4096)) << 20;
   const int acc_wgs = tn.acc_workgroups > 0 ? tn.acc_workgroups : 2048;
 
   // ---- workspace layout: constant prefix ----
