@@ -12,9 +12,10 @@ ordered band pairs per step divided by the step time; the FP32 (complex64)
 path is the headline, the FP64 path is reported beside it.
 
 Per-kernel times come from HIP events the library records on its own
-stream around every launch (a separate profiled step, after the timed
-steps).  The CPU baseline is the FP64 oracle timed on a bounded sample of
-pairs of the same workload on this host.
+stream around every launch, through the timed steps.  The roofline entry
+also quotes a measured device-to-device copy rate beside the 8 TB/s peak.
+The CPU baseline is the FP64 oracle timed on a bounded sample of pairs of
+the same workload on this host.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -112,6 +113,41 @@ def roofline(kern, stats, grid, s, peak_tflops, traffic_file=None):
     return roof
 
 
+def kernel_rates(kern, stats, grid, s):
+    """Achieved algorithmic GB/s and TFLOP/s of every kernel kind of a step."""
+    model = kernel_model(grid, s)
+    units = {k: 2 * stats["apply_fft_pairs"] for k in ("fused", "plane", "pencil", "accumulate")}
+    units.update({k: stats["energy_fft_pairs"] for k in ("energy_fused", "energy_plane", "energy_pencil")})
+    out = {}
+    for k, (ms, n) in kern.items():
+        if n == 0 or k not in model or ms <= 0:
+            continue
+        sec = ms * 1e-3
+        out[k] = {"ms": round(ms, 3), "launches": n, "gbs": round(model[k]["bytes"] * units[k] / sec / 1e9, 1),
+                  "tflops": round(model[k]["flops"] * units[k] / sec / 1e12, 3)}
+    return out
+
+
+def copy_bandwidth(device, mib=1024, reps=5):
+    """Device-to-device copy rate (bytes read + written per second) of `mib` MiB."""
+    import torch
+
+    src = torch.ones(mib << 20, dtype=torch.uint8, device=device)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def run_path(inst, prec, steps, warmup, device, profile=True):
     import torch
 
@@ -147,18 +183,26 @@ def run_path(inst, prec, steps, warmup, device, profile=True):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
+    marks = [e0]
     for i in range(steps):
         ex = step()
-        if steps > 1:
+        if i + 1 < steps:
+            mk = torch.cuda.Event(enable_timing=True)
+            mk.record(stream)
+            marks.append(mk)
             # one host sync per step keeps progress visible; it adds only a
             # launch latency between steps
             torch.cuda.synchronize()
-            log(f"  timed step {i + 1}/{steps} done")
+            if (i + 1) % 5 == 0:
+                log(f"  timed step {i + 1}/{steps} done")
     e1.record(stream)
+    marks.append(e1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / steps
-    res = dict(ms_per_step=ms, wall_s=wall, stats=st, ex=float(ex.item()))
+    per = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
+    res = dict(ms_per_step=ms, ms_median=per[steps // 2] if steps % 2 else 0.5 * (per[steps // 2 - 1] + per[steps // 2]),
+               wall_s=wall, stats=st, ex=float(ex.item()))
     if profile:
         res["kernels"] = {k: (v[0] / steps, v[1] // steps) for k, v in plan.profile_read().items()}
         plan.profile(False)
@@ -275,9 +319,9 @@ def ragged(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -318,9 +362,10 @@ def main():
     log(f"  {r32['ms_per_step']:.2f} ms/step")
     r64 = None
     if not args.no_fp64:
-        k64 = args.fp64_steps or max(1, args.steps)
-        log(f"FP64 path: {args.warmup} warm-up + {k64} timed steps")
-        r64 = run_path(inst, "c128", k64, args.warmup, device)
+        k64 = max(1, min(args.fp64_steps, args.steps))
+        w64 = min(1, args.warmup)
+        log(f"FP64 path: {w64} warm-up + {k64} timed steps")
+        r64 = run_path(inst, "c128", k64, w64, device)
         log(f"  {r64['ms_per_step']:.2f} ms/step")
 
     pairs = r32["stats"]["ordered_pairs"]
@@ -328,6 +373,9 @@ def main():
 
     roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
                     traffic_file=TRAFFIC_FILES.get(args.workload))
+    copy_gbs = copy_bandwidth(device)
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    roof["hbm_frac_vs_copy"] = round(roof["alt"]["hbm_gbs"] / copy_gbs, 4)
 
     line = {
         "metric": "band-pair Fock applications/s, FP32 vs FP64 path, + % of HBM roofline",
@@ -345,14 +393,17 @@ def main():
         "config": {"workload": WORKLOADS[cfg],
                    "ordered_pairs_per_step": pairs, "grid": list(inst.grid), "nk": inst.nk, "nbands": inst.nbands},
         "roofline": roof,
+        "ms_per_step_median": round(r32["ms_median"], 3),
         "fp32": {"ms_per_step": round(r32["ms_per_step"], 3), "pairs_per_s": round(value, 1),
                  "kernels_ms": {k: round(v[0], 3) for k, v in r32["kernels"].items() if v[1]},
+                 "kernel_rates": kernel_rates(r32["kernels"], r32["stats"], inst.grid, 8),
                  "apply_ms": round(sum(v[0] for v in r32["apply_kernels"].values()), 3)},
     }
     if r64:
         v64 = pairs / (r64["ms_per_step"] / 1e3)
         line["fp64"] = {"ms_per_step": round(r64["ms_per_step"], 3), "pairs_per_s": round(v64, 1),
                         "kernels_ms": {k: round(v[0], 3) for k, v in r64["kernels"].items() if v[1]},
+                        "kernel_rates": kernel_rates(r64["kernels"], r64["stats"], inst.grid, 16),
                         "apply_ms": round(sum(v[0] for v in r64["apply_kernels"].values()), 3)}
         line["fp32_speedup_over_fp64"] = round(r64["ms_per_step"] / r32["ms_per_step"], 3)
         line["ex_fp32_vs_fp64_rel"] = abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])

@@ -173,6 +173,44 @@ def test_beta_boron_preset_fp32_against_fp64(device):
     assert ee <= 1e-6
 
 
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_beta_boron_band_subset_against_oracle(prec, device):
+    """Beta-boron cell at its full size (72^3, 2x2x2 k-mesh) restricted to two
+    of its bands (one fully, one fractionally occupied) so that the oracle can
+    run every pair: E_x and two sampled V_x u outputs against the oracle."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    full = inputs.config("3", dtype=np.complex128, workers=16)
+    keep = [0, 155]
+    inst = inputs.Instance(full.lattice, full.grid, full.kfrac, full.kweight, full.occ[:, keep].copy(),
+                           np.ascontiguousarray(full.psi[:, keep]), full.mu)
+    del full
+    if prec == "c64":
+        inst = inst.astype(np.complex64)
+    log(f"config 3 subset {prec}: bands {keep}, f = {inst.occ[0]}")
+    plan = fock.Plan([inst], precision=prec, device=device)
+    psi = to_dev(inst.psi, device)
+    occ = to_dev(inst.occ, device)
+    (vx,), _ = plan.fock_apply([psi], [occ])
+    ex = plan.fock_energy([psi], [occ]).item()
+    torch.cuda.synchronize()
+    vx = vx.cpu().numpy()
+    plan.close()
+    o = Oracle.from_instance(inst)
+    u = inst.psi.astype(np.complex128)
+    eref = o.energy(u, inst.occ)
+    sample = [(0, 0), (5, 1)]
+    vref, _ = o.apply(u, inst.occ, outputs=sample)
+    tol = (1e-12, 1e-12) if prec == "c128" else (1e-6, 1e-5)
+    ee = abs(ex - eref) / abs(eref)
+    ev = max(np.linalg.norm(vx[k, n] - vref[k, n]) / np.linalg.norm(vref[k, n]) for k, n in sample)
+    log(f"  E_x err {ee:.2e}  V_x err {ev:.2e}")
+    assert ee <= tol[0]
+    assert ev <= tol[1]
+
+
 def test_ragged_batch_one_graph_against_single_fp64(device):
     """48 independent instances of uneven grids, band counts and k-meshes in
     one plan replayed as one graph (FP32), against one-at-a-time FP64 plans;
