@@ -219,21 +219,15 @@ def run_path(inst, prec, steps, warmup, device, profile=True):
     return res
 
 
-def cpu_baseline(inst, seconds):
-    """FP64 oracle on a bounded sample: all partners (k', m) of outputs
-    (k=0, n), in order, until `seconds` of CPU time have passed."""
+def _oracle_sample(inst, seconds):
+    """(pairs, seconds, last n): all partners (k', m) of outputs (k=0, n), in
+    order, until `seconds` have passed."""
     from oracle.fock_oracle import Oracle
 
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
     psi = inst.psi.astype(np.complex128)
     o = Oracle.from_instance(inst)
     npairs = 0
     t0 = time.perf_counter()
-    done = False
     for n in range(inst.nbands):
         for kp in range(inst.nk):
             v = o.v(0, kp)
@@ -241,13 +235,29 @@ def cpu_baseline(inst, seconds):
                 o.pair(psi[0, n], psi[kp, m], v)
                 npairs += 1
             if time.perf_counter() - t0 > seconds:
-                done = True
-                break
-        if done:
-            break
-    el = time.perf_counter() - t0
-    return dict(value=npairs / el, unit="ordered band pairs/s (apply+energy per pair, FP64)", cores=threads,
-                kind="oracle", sample=f"{npairs} ordered pairs (outputs k=0, n<= {n}; every k', m) in {el:.1f} s")
+                return npairs, time.perf_counter() - t0, n
+    return npairs, time.perf_counter() - t0, inst.nbands - 1
+
+
+def cpu_baseline(inst, seconds, seconds_1t=5.0):
+    """FP64 oracle on a bounded sample of the workload, with every BLAS thread
+    of the host, and (beside it) with one thread."""
+    threads = os.cpu_count() or 1
+    single = None
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        with threadpool_limits(limits=1):
+            p1, t1, _ = _oracle_sample(inst, seconds_1t)
+        single = {"value": p1 / t1, "cores": 1, "sample": f"{p1} ordered pairs in {t1:.1f} s"}
+    except ImportError:
+        pass
+    npairs, el, n = _oracle_sample(inst, seconds)
+    out = dict(value=npairs / el, unit="ordered band pairs/s (apply+energy per pair, FP64)", cores=threads,
+               kind="oracle", sample=f"{npairs} ordered pairs (outputs k=0, n<= {n}; every k', m) in {el:.1f} s")
+    if single:
+        out["single_thread"] = single
+    return out
 
 
 def ragged(args):
