@@ -142,6 +142,55 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
 fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const double* const* occ,
                                  const double* grad_ex, double scale, void* const* grad_psi);
 
+/* ---- plane-wave boundary and batched 3-D DFT ------------------------------
+ * A plane-wave code keeps each orbital as coefficients c(G) on the cutoff
+ * sphere |k+G|^2/2 < E_cut and scatters them to the FFT grid around the
+ * band-pair loop, gathering the results back (paper, "CPU Performance
+ * Analysis": the scatter/gather of FOCK_ACC).  With
+ *   psi(r) = Omega^-1/2 sum_G c(G) exp(i (k+G).r),  u = psi exp(-i k.r):
+ *   to the grid    u[j] = Omega^-1/2 sum_G c(G) exp(+2 pi i sum_d c_d j_d / N_d)
+ *   to the sphere  d(G) = (Omega^1/2 / N) sum_j f[j] exp(-2 pi i sum_d c_d j_d / N_d)
+ * where c_d = g_d mod N_d is the grid class of G; d(G) is the exact
+ * coefficient of f on the sphere, so sum_G conj(c_m(G)) d_n(G) equals the
+ * grid overlap Omega/N sum_j conj(u_m[j]) f_n[j] for band-limited u_m.
+ *
+ * Sphere of instance i, all device memory owned by the caller:
+ *   gidx[i]     int32 [nk][npw_max[i]]: flat grid class (c1 N2 + c2) N3 + c3
+ *               of slot p of k; slots must be distinct within a k
+ *   npw[i]      int32 [nk]: slots in use per k (values above npw_max[i] are
+ *               read as npw_max[i])
+ *   npw_max[i]  host int32 >= 1, slots per k
+ *   coefficients: plan precision, [nk][nbands][npw_max[i]]
+ * Slots whose class lies outside [0, N) are skipped by the scatter and read
+ * as zero by the gather; nothing outside the arrays is touched.
+ * All calls are asynchronous on the plan stream; argument errors are
+ * reported before any launch. */
+
+/* u (psi layout, written in full) from sphere coefficients coef. */
+fock_status fock_pw_to_grid(fock_plan_t plan, const void* const* coef, const int32_t* const* gidx,
+                            const int32_t* const* npw, const int32_t* npw_max, void* const* psi);
+
+/* Sphere coefficients coef_out[i] ([nk][nbands][npw_max], slots past npw[k]
+ * written as zero) of the grid functions f[i] (psi layout).  f is
+ * overwritten: it is transformed in place. */
+fock_status fock_grid_to_pw(fock_plan_t plan, void* const* f, const int32_t* const* gidx, const int32_t* const* npw,
+                            const int32_t* npw_max, void* const* coef_out);
+
+/* V_x psi on the sphere: fock_pw_to_grid(coef -> psi_work),
+ * fock_apply(psi_work -> vx_work), fock_grid_to_pw(vx_work -> vx_coef).
+ * psi_work and vx_work are caller buffers in the psi layout (distinct);
+ * on return psi_work holds u and vx_work its transformed V_x u. */
+fock_status fock_apply_pw(fock_plan_t plan, const void* const* coef, const int32_t* const* gidx,
+                          const int32_t* const* npw, const int32_t* npw_max, const double* const* occ,
+                          void* const* psi_work, void* const* vx_work, void* const* vx_coef);
+
+/* In-place unnormalised 3-D DFT of `count` grids of instance `inst`'s shape
+ * in the plan precision: grid b starts at data + b * stride elements
+ * (stride >= N), element j = (j1 N2 + j2) N3 + j3.
+ *   sign -1: F(c) = sum_j f(j) exp(-2 pi i sum_d c_d j_d / N_d)
+ *   sign +1: the same with exp(+...), no 1/N. */
+fock_status fock_dft3(fock_plan_t plan, int32_t inst, int32_t sign, int64_t count, void* data, int64_t stride);
+
 /* Counters of the plan: ordered band pairs per apply (N_k^2 N_b^2 summed over
  * instances, or per the k-pair lists), band-pair FFT round trips per apply,
  * FFT pairs per energy evaluation, and kernel launches per apply. */
@@ -160,7 +209,9 @@ typedef enum {
   FOCK_K_OTHER = 7,          /* zero fill of outputs without partners              */
   FOCK_K_FUSED = 8,          /* apply: whole pair per workgroup (cubic <= 32^3)    */
   FOCK_K_ENERGY_FUSED = 9,   /* energy: whole pair per workgroup (cubic <= 32^3)   */
-  FOCK_K_COUNT = 10
+  FOCK_K_DFT = 10,           /* batched 3-D DFT passes (fock_dft3, plane waves)    */
+  FOCK_K_PW = 11,            /* scatter / gather between cutoff sphere and grid    */
+  FOCK_K_COUNT = 12
 } fock_kernel_kind;
 
 /* Per-kernel timing: when enabled, every launch is bracketed by HIP events on

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfock.so")
-SOURCES = ["kernels.hip", "pair_fused.hip", "overlap_mfma.hip", "pass_reg.hip", "plan.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "pair_fused.hip", "overlap_mfma.hip", "pass_reg.hip", "pw_fft.hip", "plan.cpp", "api.cpp"]
 ARCH = os.environ.get("FOCK_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

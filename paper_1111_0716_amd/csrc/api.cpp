@@ -168,6 +168,38 @@ std::vector<uintptr_t> ptr_key(const Plan* p, std::initializer_list<const void* 
 
 using namespace fock;
 
+namespace {
+
+fock_status check_sphere(const Plan* p, const int32_t* const* gidx, const int32_t* const* npw,
+                         const int32_t* npw_max) {
+  if (!gidx || !npw || !npw_max) return set_error(FOCK_ERR_ARG, "gidx, npw or npw_max is NULL");
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    if (!gidx[i] || !npw[i]) return set_error(FOCK_ERR_ARG, "gidx or npw of instance " + std::to_string(i) + " is NULL");
+    if (npw_max[i] < 1) return set_error(FOCK_ERR_ARG, "npw_max of instance " + std::to_string(i) + " < 1");
+  }
+  return FOCK_OK;
+}
+
+fock_status run_pw_to_grid(Plan* p, const void* const* coef, const int32_t* const* gidx, const int32_t* const* npw,
+                           const int32_t* npw_max, void* const* psi) {
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    const hipError_t e = launch_pw_to_grid(*p, static_cast<int>(i), coef[i], gidx[i], npw[i], npw_max[i], psi[i]);
+    if (e != hipSuccess) return hip_fail(e, "sphere-to-grid launch");
+  }
+  return FOCK_OK;
+}
+
+fock_status run_grid_to_pw(Plan* p, void* const* f, const int32_t* const* gidx, const int32_t* const* npw,
+                           const int32_t* npw_max, void* const* coef) {
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    const hipError_t e = launch_grid_to_pw(*p, static_cast<int>(i), f[i], gidx[i], npw[i], npw_max[i], coef[i]);
+    if (e != hipSuccess) return hip_fail(e, "grid-to-sphere launch");
+  }
+  return FOCK_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision prec, void* hip_stream,
@@ -349,6 +381,65 @@ fock_status fock_set_graph(fock_plan_t plan, int enable) {
     p->g_backward.release();
   }
   return FOCK_OK;
+}
+
+fock_status fock_pw_to_grid(fock_plan_t plan, const void* const* coef, const int32_t* const* gidx,
+                            const int32_t* const* npw, const int32_t* npw_max, void* const* psi) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, coef, "coef")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(psi), "psi")) != FOCK_OK) return s;
+  if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
+  return run_pw_to_grid(p, coef, gidx, npw, npw_max, psi);
+}
+
+fock_status fock_grid_to_pw(fock_plan_t plan, void* const* f, const int32_t* const* gidx, const int32_t* const* npw,
+                            const int32_t* npw_max, void* const* coef_out) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(f), "f")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(coef_out), "coef_out")) != FOCK_OK) return s;
+  if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
+  return run_grid_to_pw(p, f, gidx, npw, npw_max, coef_out);
+}
+
+fock_status fock_apply_pw(fock_plan_t plan, const void* const* coef, const int32_t* const* gidx,
+                          const int32_t* const* npw, const int32_t* npw_max, const double* const* occ,
+                          void* const* psi_work, void* const* vx_work, void* const* vx_coef) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, coef, "coef")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(psi_work), "psi_work")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_work), "vx_work")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_coef), "vx_coef")) != FOCK_OK) return s;
+  if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (psi_work[i] == vx_work[i]) return set_error(FOCK_ERR_ARG, "psi_work aliases vx_work");
+  if ((s = run_pw_to_grid(p, coef, gidx, npw, npw_max, psi_work)) != FOCK_OK) return s;
+  if ((s = run_apply(p, psi_work, occ, vx_work, nullptr, 1.0, false)) != FOCK_OK) return s;
+  return run_grid_to_pw(p, vx_work, gidx, npw, npw_max, vx_coef);
+}
+
+fock_status fock_dft3(fock_plan_t plan, int32_t inst, int32_t sign, int64_t count, void* data, int64_t stride) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if (inst < 0 || static_cast<size_t>(inst) >= p->inst.size()) return set_error(FOCK_ERR_ARG, "instance out of range");
+  if (sign != -1 && sign != 1) return set_error(FOCK_ERR_ARG, "sign must be -1 or +1");
+  if (count < 0) return set_error(FOCK_ERR_ARG, "count < 0");
+  if (count == 0) return FOCK_OK;
+  if (!data) return set_error(FOCK_ERR_ARG, "data is NULL");
+  if (stride < p->inst[inst].npts) return set_error(FOCK_ERR_ARG, "stride smaller than the grid");
+  const hipError_t e = launch_dft3(*p, inst, sign, count, data, stride);
+  return e == hipSuccess ? FOCK_OK : hip_fail(e, "3-D DFT launch");
 }
 
 fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* apply_fft_pairs,

@@ -136,6 +136,13 @@ hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, co
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 hipError_t launch_energy_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
+hipError_t launch_zero_all_bands(const Plan& p, int inst, void* out);
+void prepare_dft_kernels(fock_precision prec, int lim);
+hipError_t launch_dft3(const Plan& p, int inst, int sign, long long count, void* data, long long stride);
+hipError_t launch_pw_to_grid(const Plan& p, int inst, const void* coef, const int* gidx, const int* npw, int npw_max,
+                             void* psi);
+hipError_t launch_grid_to_pw(const Plan& p, int inst, void* f, const int* gidx, const int* npw, int npw_max,
+                             void* coef);
 hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ, int n2);
 // whole-pair path (pair_fused.hip)
 bool fused_supported(fock_precision prec, const int grid[3]);

@@ -381,6 +381,25 @@ hipError_t zero_outputs_t(const Plan& p, int inst, void* out) {
 
 }  // namespace
 
+hipError_t launch_zero_all_bands(const Plan& p, int inst, void* out) {
+  const Instance& in = p.inst[inst];
+  const int gx = static_cast<int>(std::min<long long>(1024, (in.npts + kBlock - 1) / kBlock));
+  const int nbt = in.nk * in.nbands;
+  for (int b0 = 0; b0 < nbt; b0 += 65535) {
+    const int nb = std::min(65535, nbt - b0);
+    p.prof.begin(FOCK_K_OTHER, p.stream);
+    if (p.prec == FOCK_C128) {
+      hipLaunchKernelGGL((k_zero_bands<double>), dim3(gx, nb), dim3(kBlock), 0, p.stream, static_cast<double2*>(out),
+                         b0, static_cast<long long>(in.band_stride), static_cast<long long>(in.npts));
+    } else {
+      hipLaunchKernelGGL((k_zero_bands<float>), dim3(gx, nb), dim3(kBlock), 0, p.stream, static_cast<float2*>(out),
+                         b0, static_cast<long long>(in.band_stride), static_cast<long long>(in.npts));
+    }
+    p.prof.end(FOCK_K_OTHER, p.stream);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out) {
   return p.prec == FOCK_C128 ? zero_outputs_t<double>(p, inst, out) : zero_outputs_t<float>(p, inst, out);
 }
@@ -393,6 +412,7 @@ hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
   *max_lds = static_cast<size_t>(lim);
   prepare_fused_kernels(prec, lim - 256);
   prepare_reg_kernels(prec, lim - 64);
+  prepare_dft_kernels(prec, lim - 64);
   if (lim > 65536) {
     if (prec == FOCK_C128)
       allow_large_lds<double>(lim - 64);

@@ -21,10 +21,11 @@ FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FO
 FOCK_C128, FOCK_C64 = 0, 1
 
 EXPORTED = ["fock_plan", "fock_plan_tuned", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
-            "fock_energy", "fock_energy_backward", "fock_plan_stats", "fock_profile_enable", "fock_profile_read",
-            "fock_set_graph", "fock_destroy", "fock_status_string", "fock_last_error"]
+            "fock_energy", "fock_energy_backward", "fock_pw_to_grid", "fock_grid_to_pw", "fock_apply_pw", "fock_dft3",
+            "fock_plan_stats", "fock_profile_enable", "fock_profile_read", "fock_set_graph", "fock_destroy",
+            "fock_status_string", "fock_last_error"]
 KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
-                "other", "fused", "energy_fused"]
+                "other", "fused", "energy_fused", "dft", "pw"]
 
 
 class FockError(RuntimeError):
@@ -72,6 +73,13 @@ def lib():
         L.fock_energy.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]
         L.fock_energy_backward.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_double,
                                            POINTER(c_void_p)]
+        L.fock_pw_to_grid.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                       POINTER(c_int32), POINTER(c_void_p)]
+        L.fock_grid_to_pw.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                       POINTER(c_int32), POINTER(c_void_p)]
+        L.fock_apply_pw.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), POINTER(c_int32),
+                                     POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p)]
+        L.fock_dft3.argtypes = [c_void_p, c_int32, c_int32, c_int64, c_void_p, c_int64]
         L.fock_plan_stats.argtypes = [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
                                       POINTER(c_int64)]
         L.fock_profile_enable.argtypes = [c_void_p, c_int]
@@ -237,6 +245,94 @@ class Plan:
                                          _ptrs([o.data_ptr() for o in occ]), c_void_p(g.data_ptr()),
                                          float(scale), _ptrs([x.data_ptr() for x in out])))
         return out
+
+    # ---- plane-wave boundary and batched 3-D DFT -------------------------
+    def _sphere(self, gidx, npw):
+        """Validate the per-instance sphere tensors; returns (gidx, npw, npw_max array)."""
+        gidx, npw = _aslist(gidx), _aslist(npw)
+        t = self.torch
+        for i, (g, n) in enumerate(zip(gidx, npw)):
+            m = self.meta[i]
+            if not (g.is_cuda and g.dtype == t.int32 and g.is_contiguous() and g.dim() == 2 and g.shape[0] == m["nk"]):
+                raise ValueError(f"gidx[{i}] must be a contiguous int32 CUDA tensor [nk, npw_max]")
+            if not (n.is_cuda and n.dtype == t.int32 and n.is_contiguous() and tuple(n.shape) == (m["nk"],)):
+                raise ValueError(f"npw[{i}] must be a contiguous int32 CUDA tensor [nk]")
+        npw_max = (c_int32 * len(gidx))(*[int(g.shape[1]) for g in gidx])
+        return gidx, npw, npw_max
+
+    def _check_coef(self, c, i, npw_max):
+        m = self.meta[i]
+        if not (c.is_cuda and c.dtype == self.cdtype and c.is_contiguous() and
+                tuple(c.shape) == (m["nk"], m["nbands"], npw_max)):
+            raise ValueError(f"coefficients[{i}] must be a contiguous {self.cdtype} CUDA tensor "
+                             f"({m['nk']}, {m['nbands']}, {npw_max})")
+
+    def pw_to_grid(self, coef, gidx, npw, out=None):
+        """Orbitals on the grid from sphere coefficients (see fock_pw_to_grid)."""
+        coef = _aslist(coef)
+        gidx, npw, npw_max = self._sphere(gidx, npw)
+        for i, c in enumerate(coef):
+            self._check_coef(c, i, npw_max[i])
+        out = [self.torch.empty((m["nk"], m["nbands"], m["npts"]), dtype=self.cdtype, device=self.device)
+               for m in self.meta] if out is None else _aslist(out)
+        for i, o in enumerate(out):
+            self._check_psi(o, i)
+        self._sync_stream()
+        check(lib().fock_pw_to_grid(self.handle, _ptrs([c.data_ptr() for c in coef]), _ptrs([g.data_ptr() for g in gidx]),
+                                    _ptrs([n.data_ptr() for n in npw]), npw_max, _ptrs([o.data_ptr() for o in out])))
+        return out
+
+    def grid_to_pw(self, f, gidx, npw, out=None):
+        """Sphere coefficients of grid functions f (f is transformed in place)."""
+        f = _aslist(f)
+        gidx, npw, npw_max = self._sphere(gidx, npw)
+        for i, x in enumerate(f):
+            self._check_psi(x, i)
+        out = [self.torch.empty((m["nk"], m["nbands"], npw_max[i]), dtype=self.cdtype, device=self.device)
+               for i, m in enumerate(self.meta)] if out is None else _aslist(out)
+        for i, c in enumerate(out):
+            self._check_coef(c, i, npw_max[i])
+        self._sync_stream()
+        check(lib().fock_grid_to_pw(self.handle, _ptrs([x.data_ptr() for x in f]), _ptrs([g.data_ptr() for g in gidx]),
+                                    _ptrs([n.data_ptr() for n in npw]), npw_max, _ptrs([c.data_ptr() for c in out])))
+        return out
+
+    def fock_apply_pw(self, coef, gidx, npw, occ, psi_work=None, vx_work=None, out=None):
+        """V_x psi on the sphere; returns (coefficients, psi_work, vx_work)."""
+        coef, occ = _aslist(coef), _aslist(occ)
+        gidx, npw, npw_max = self._sphere(gidx, npw)
+        t = self.torch
+        for i, (c, o) in enumerate(zip(coef, occ)):
+            self._check_coef(c, i, npw_max[i])
+            self._check_occ(o, i)
+
+        def grids():
+            return [t.empty((m["nk"], m["nbands"], m["npts"]), dtype=self.cdtype, device=self.device) for m in self.meta]
+
+        psi_work = grids() if psi_work is None else _aslist(psi_work)
+        vx_work = grids() if vx_work is None else _aslist(vx_work)
+        out = [t.empty_like(c) for c in coef] if out is None else _aslist(out)
+        for i in range(len(coef)):
+            self._check_psi(psi_work[i], i)
+            self._check_psi(vx_work[i], i)
+            self._check_coef(out[i], i, npw_max[i])
+        self._sync_stream()
+        check(lib().fock_apply_pw(self.handle, _ptrs([c.data_ptr() for c in coef]), _ptrs([g.data_ptr() for g in gidx]),
+                                  _ptrs([n.data_ptr() for n in npw]), npw_max, _ptrs([o.data_ptr() for o in occ]),
+                                  _ptrs([x.data_ptr() for x in psi_work]), _ptrs([x.data_ptr() for x in vx_work]),
+                                  _ptrs([x.data_ptr() for x in out])))
+        return out, psi_work, vx_work
+
+    def dft3(self, data, sign, inst=0):
+        """In-place unnormalised 3-D DFT of every grid in ``data`` (a contiguous
+        complex tensor [..., N] of the plan precision on the instance's grid)."""
+        m = self.meta[inst]
+        if not (data.is_cuda and data.dtype == self.cdtype and data.is_contiguous() and data.numel() % m["npts"] == 0):
+            raise ValueError(f"data must be a contiguous {self.cdtype} CUDA tensor of whole grids of {m['npts']} points")
+        self._sync_stream()
+        check(lib().fock_dft3(self.handle, int(inst), int(sign), data.numel() // m["npts"], c_void_p(data.data_ptr()),
+                              m["npts"]))
+        return data
 
     def stats(self):
         a, b, c, d = c_int64(), c_int64(), c_int64(), c_int64()

@@ -104,6 +104,11 @@ def test_calls_before_workspace_are_state_errors():
     assert L.fock_apply(h, one, one, one, None) == fock.FOCK_ERR_STATE
     assert L.fock_energy(h, one, one, ctypes.c_void_p(1)) == fock.FOCK_ERR_STATE
     assert L.fock_energy_backward(h, one, one, ctypes.c_void_p(1), 1.0, one) == fock.FOCK_ERR_STATE
+    npw_max = (ctypes.c_int32 * 1)(4)
+    assert L.fock_pw_to_grid(h, one, one, one, npw_max, one) == fock.FOCK_ERR_STATE
+    assert L.fock_grid_to_pw(h, one, one, one, npw_max, one) == fock.FOCK_ERR_STATE
+    assert L.fock_apply_pw(h, one, one, one, npw_max, one, one, fock._ptrs([2]), one) == fock.FOCK_ERR_STATE
+    assert L.fock_dft3(h, 0, -1, 1, ctypes.c_void_p(1), 512) == fock.FOCK_ERR_STATE
     # misaligned / undersized workspace are argument errors detected on the host
     assert L.fock_set_workspace(h, ctypes.c_void_p(3), 1 << 30) == fock.FOCK_ERR_ARG
     assert L.fock_set_workspace(h, ctypes.c_void_p(256), 16) == fock.FOCK_ERR_NOMEM
