@@ -326,6 +326,134 @@ def ragged(args):
     print(json.dumps(line), flush=True)
 
 
+def fft3d(args):
+    """Batched 3-D DFT (fock_dft3, forward, in place) per cubic size: GPU rate
+    with the data resident in HBM, beside scipy's FFT on every host core; one
+    grid and a batch of about 256 MiB per size."""
+    import scipy.fft
+    import torch
+
+    from paper_1111_0716_amd import fock, inputs
+
+    device = torch.device("cuda:0")
+    cores = os.cpu_count() or 1
+    rows = []
+    for L in (16, 24, 32, 48, 64, 72):
+        n = L ** 3
+        inst = inputs.small_instance(grid=(L, L, L), kmesh=(1, 1, 1), nbands=1, seed=(400, L))
+        plan = fock.Plan([inst], precision="c64", device=device)
+        batch = max(1, (256 << 20) // (8 * n))
+        x = torch.randn(batch, n, dtype=torch.complex64, device=device)
+        plan.dft3(x, -1)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            plan.dft3(x, -1)
+        e1.record()
+        torch.cuda.synchronize()
+        gpu_us = e0.elapsed_time(e1) * 1e3 / (reps * batch)
+        one = x[:1].clone()
+        plan.dft3(one, -1)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            plan.dft3(one, -1)
+        e1.record()
+        torch.cuda.synchronize()
+        gpu1_us = e0.elapsed_time(e1) * 1e3 / reps
+        plan.close()
+        del x, one
+        torch.cuda.empty_cache()
+        hb = min(batch, 32)
+        h = (np.random.default_rng(L).standard_normal((hb, L, L, L)) + 0j).astype(np.complex64)
+        scipy.fft.fftn(h[:1], axes=(1, 2, 3), workers=cores)
+        t0 = time.perf_counter()
+        scipy.fft.fftn(h, axes=(1, 2, 3), workers=cores)
+        cpu_us = (time.perf_counter() - t0) * 1e6 / hb
+        t0 = time.perf_counter()
+        scipy.fft.fftn(h[:1], axes=(1, 2, 3), workers=cores)
+        cpu1_us = (time.perf_counter() - t0) * 1e6
+        flops = 5.0 * n * math.log2(n)
+        byts = 4.0 * 8 * n  # two passes, each reads and writes the grid
+        rows.append({"grid": L, "batch": batch, "gpu_us_per_grid": round(gpu_us, 3), "gpu_us_one_grid": round(gpu1_us, 2),
+                     "cpu_us_per_grid": round(cpu_us, 2), "cpu_us_one_grid": round(cpu1_us, 2),
+                     "gbs": round(byts / (gpu_us * 1e-6) / 1e9, 1), "tflops": round(flops / (gpu_us * 1e-6) / 1e12, 3)})
+        log(f"  {L}^3: GPU {gpu_us:.2f} us/grid (one grid {gpu1_us:.1f} us), CPU {cpu_us:.1f} us/grid")
+    top = rows[-1]
+    cross = next((r["grid"] for r in rows if r["gpu_us_one_grid"] < r["cpu_us_one_grid"]), None)
+    line = {"metric": "batched 3-D DFT rate (complex64, forward, in place)", "value": round(1e6 / top["gpu_us_per_grid"], 1),
+            "unit": f"grids/s at {top['grid']}^3", "n_gpus": 1, "steps": 5, "warmup": 1,
+            "ms_per_step": round(top["gpu_us_per_grid"] * top["batch"] / 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 complex)", "data": "synthetic (normal)",
+            "config": {"workload": "batched cubic 3-D DFT, 16^3-72^3, ~256 MiB per batch"},
+            "roofline": {"bound": "hbm", "achieved": top["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(top["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "dft (plane + pencil passes)", "bytes_per_grid": 4 * 8 * top["grid"] ** 3},
+            "cpu_baseline": {"value": round(1e6 / top["cpu_us_per_grid"], 1), "unit": f"grids/s at {top['grid']}^3",
+                             "cores": cores, "kind": "scipy.fft.fftn", "sample": "batch of up to 32 grids"},
+            "sizes": rows, "single_grid_gpu_faster_from": cross}
+    print(json.dumps(line), flush=True)
+
+
+def pw(args):
+    """V_x psi on the plane-wave sphere (fock_apply_pw) against the grid
+    apply, FP32, alpha-boron workload: the cost of the sphere boundary."""
+    import torch
+
+    from paper_1111_0716_amd import fock, inputs
+
+    device = torch.device("cuda:0")
+    inst = inputs.config("2", dtype=np.complex128, workers=16).astype(np.complex64)
+    g = [inputs.sphere_indices(inst.lattice, inst.kfrac[k], inst.ecut, inst.grid) for k in range(inst.nk)]
+    npw = np.array([len(x) for x in g], dtype=np.int32)
+    npw_max = int(npw.max())
+    gidx = np.full((inst.nk, npw_max), -1, dtype=np.int32)
+    n1, n2, n3 = inst.grid
+    for k, x in enumerate(g):
+        gidx[k, : len(x)] = ((x[:, 0] % n1) * n2 + (x[:, 1] % n2)) * n3 + (x[:, 2] % n3)
+    plan = fock.Plan([inst], precision="c64", device=device)
+    psi = torch.from_numpy(inst.psi).to(device)
+    occ = torch.from_numpy(inst.occ).to(device)
+    g_d, n_d = torch.from_numpy(gidx).to(device), torch.from_numpy(npw).to(device)
+    (coef,) = plan.grid_to_pw([psi.clone()], [g_d], [n_d])
+    work_u, work_v = torch.empty_like(psi), torch.empty_like(psi)
+    out = torch.empty_like(coef)
+    vx = torch.empty_like(psi)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_grid = timed(lambda: plan.fock_apply([psi], [occ], out=[vx]))
+    ms_pw = timed(lambda: plan.fock_apply_pw([coef], [g_d], [n_d], [occ], psi_work=[work_u], vx_work=[work_v],
+                                             out=[out]))
+    plan.profile(True)
+    plan.fock_apply_pw([coef], [g_d], [n_d], [occ], psi_work=[work_u], vx_work=[work_v], out=[out])
+    torch.cuda.synchronize()
+    kern = {k: round(v[0], 3) for k, v in plan.profile_read().items() if v[1]}
+    plan.profile(False)
+    pairs = plan.stats()["ordered_pairs"]
+    line = {"metric": "band-pair Fock applications/s on the plane-wave sphere (FP32)",
+            "value": round(pairs / (ms_pw / 1e3), 1), "unit": "ordered band pairs/s (fock_apply_pw)", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": round(ms_pw, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 complex)", "data": "synthetic",
+            "config": {"workload": WORKLOADS["2"] + ", coefficients on the 12 Ha sphere",
+                       "npw": [int(npw.min()), int(npw.max())]},
+            "grid_apply_ms": round(ms_grid, 3), "boundary_overhead": round(ms_pw / ms_grid - 1.0, 4),
+            "kernels_ms": kern}
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,7 +463,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged"], default="alpha")
+    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw"], default="alpha")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (the reference dispatch "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -347,6 +475,10 @@ def main():
 
     if args.workload == "ragged":
         return ragged(args)
+    if args.workload == "fft3d":
+        return fft3d(args)
+    if args.workload == "pw":
+        return pw(args)
 
     import torch
 
