@@ -95,7 +95,9 @@ fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision pre
  *   tbuf_mb         three-pass path: pair-buffer budget (MiB), which bounds
  *                   |O| x |P| pairs per batch
  *   fused_split     whole-pair path: partner slices per output (1..4)
- *   no_fused        1: use the three-pass path for every grid */
+ *   no_fused        1: use the three-pass path for every grid
+ * Defaults: acc_workgroups 2048, tbuf_mb 4096 (or $FOCK_TBUF_MB), fused_split
+ * chosen to fill the compute units evenly. */
 typedef struct {
   int32_t acc_workgroups;
   int32_t tbuf_mb;
@@ -206,7 +208,7 @@ typedef enum {
   FOCK_K_ENERGY_PENCIL = 4,  /* energy: FFT of axis 1 + FP64 sum of v_q |P|^2      */
   FOCK_K_ENERGY_REDUCE = 5,  /* energy: fixed-order reductions                     */
   FOCK_K_OVERLAP = 6,        /* band overlap M                                     */
-  FOCK_K_OTHER = 7,          /* zero fill of outputs without partners              */
+  FOCK_K_OTHER = 7,          /* zero fills, sums of partner-slice partial outputs  */
   FOCK_K_FUSED = 8,          /* apply: whole pair per workgroup (cubic <= 32^3)    */
   FOCK_K_ENERGY_FUSED = 9,   /* energy: whole pair per workgroup (cubic <= 32^3)   */
   FOCK_K_DFT = 10,           /* batched 3-D DFT passes (fock_dft3, plane waves)    */
