@@ -138,6 +138,9 @@ hipError_t launch_energy_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
 hipError_t launch_zero_all_bands(const Plan& p, int inst, void* out);
 void prepare_dft_kernels(fock_precision prec, int lim);
+bool reg_dft_supported(fock_precision prec, const int grid[3]);
+void prepare_reg_dft_kernels(fock_precision prec, int lim);
+hipError_t launch_reg_dft3(const Plan& p, int inst, int sign, int count, void* data, long long stride);
 hipError_t launch_dft3(const Plan& p, int inst, int sign, long long count, void* data, long long stride);
 hipError_t launch_pw_to_grid(const Plan& p, int inst, const void* coef, const int* gidx, const int* npw, int npw_max,
                              void* psi);

@@ -320,6 +320,53 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
 }
 
 // ---------------------------------------------------------------------------
+// plain batched 3-D DFT in the natural layout (fock_dft3 on cubic grids)
+// ---------------------------------------------------------------------------
+// plane pass: axes 2 and 3 of plane j1, read and written as columns (one
+// line per lane, coalesced); two transposes bring the rows in and back out
+template <typename T, int L, int S>
+__global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE)) void k_dft_plane_reg(
+    typename cx<T>::t* __restrict__ data, long long stride) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  constexpr int LL = L * L;
+  extern __shared__ unsigned char smem_raw[];
+  const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
+  const int j1 = blockIdx.x * Sh::PL + pl;
+  const bool valid = j1 < L;
+  T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
+  C* g = data + static_cast<size_t>(blockIdx.y) * stride + static_cast<size_t>(j1) * LL + col;
+  C x[L];
+#pragma unroll
+  for (int j2 = 0; j2 < L; ++j2) x[j2] = valid ? g[j2 * L] : C{T(0), T(0)};
+  reg_fft<C, L, S>(x);                  // axis 2: x[c2] at j3 = col
+  transpose_plane<C, T, L>(x, sp, col);  // row c2 = col
+  reg_fft<C, L, S>(x);                  // axis 3: x[c3]
+  transpose_plane<C, T, L>(x, sp, col);  // column c3 = col: x[c2]
+  if (valid) {
+#pragma unroll
+    for (int c2 = 0; c2 < L; ++c2) g[c2 * L] = x[c2];
+  }
+}
+
+// pencil pass: axis 1 of line (c2, c3) = l, coalesced across lanes
+template <typename T, int L, int S>
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_dft_pencil_reg(
+    typename cx<T>::t* __restrict__ data, long long stride) {
+  using C = typename cx<T>::t;
+  constexpr int LL = L * L;
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= LL) return;  // no barrier in this kernel
+  C* g = data + static_cast<size_t>(blockIdx.y) * stride + l;
+  C x[L];
+#pragma unroll
+  for (int j1 = 0; j1 < L; ++j1) x[j1] = g[static_cast<size_t>(j1) * LL];
+  reg_fft<C, L, S>(x);
+#pragma unroll
+  for (int c1 = 0; c1 < L; ++c1) g[static_cast<size_t>(c1) * LL] = x[c1];
+}
+
+// ---------------------------------------------------------------------------
 // two-lane lines (L >= 64 FP32, L >= 40 FP64): each line lives in a lane pair
 // ---------------------------------------------------------------------------
 // The lanes 2i and 2i+1 share a line; lane h holds the samples 2m + h, or
@@ -689,6 +736,33 @@ hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const do
   return hipErrorInvalidValue;
 }
 
+template <typename T, int L>
+hipError_t reg_dft3_L(const Plan& p, int sign, int count, void* data, long long stride) {
+  using C = typename cx<T>::t;
+  using Sh = RegShape<T, L>;
+  C* d = static_cast<C*>(data);
+  if (sign < 0) {
+    hipLaunchKernelGGL((k_dft_plane_reg<T, L, -1>), dim3(Sh::NG, count), dim3(Sh::NTP), Sh::LDS, p.stream, d, stride);
+    hipLaunchKernelGGL((k_dft_pencil_reg<T, L, -1>), dim3(Sh::NLB, count), dim3(256), 0, p.stream, d, stride);
+  } else {
+    hipLaunchKernelGGL((k_dft_plane_reg<T, L, +1>), dim3(Sh::NG, count), dim3(Sh::NTP), Sh::LDS, p.stream, d, stride);
+    hipLaunchKernelGGL((k_dft_pencil_reg<T, L, +1>), dim3(Sh::NLB, count), dim3(256), 0, p.stream, d, stride);
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int L>
+void dft_reg_lds_attr(int lim) {
+  const void* fs[] = {reinterpret_cast<const void*>(&k_dft_plane_reg<T, L, -1>),
+                      reinterpret_cast<const void*>(&k_dft_plane_reg<T, L, +1>)};
+  for (const void* f : fs)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+}
+
+// the lengths with one-lane DFT kernels, per precision (longer FP64 lines would spill)
+#define FOCK_DFT_F32(X) X(24) X(32) X(40) X(48) X(64) X(72)
+#define FOCK_DFT_F64(X) X(24) X(32)
+
 }  // namespace
 
 bool reg_supported(fock_precision prec, const int grid[3]) {
@@ -713,6 +787,39 @@ void prepare_reg_kernels(fock_precision prec, int lim) {
 #define CASE(N) \
   if (prec == FOCK_C64) reg_lds_attr<float, N>(lim); else reg_lds_attr<double, N>(lim);
   FOCK_REG_L(CASE)
+#undef CASE
+}
+
+bool reg_dft_supported(fock_precision prec, const int grid[3]) {
+  if (grid[0] != grid[1] || grid[0] != grid[2]) return false;
+  switch (grid[0]) {
+    case 24: case 32: return true;
+    case 40: case 48: case 64: case 72: return prec == FOCK_C64;
+    default: return false;
+  }
+}
+
+hipError_t launch_reg_dft3(const Plan& p, int inst, int sign, int count, void* data, long long stride) {
+  const int L = p.inst[inst].grid[0];
+#define CASE(N) \
+  case N: return reg_dft3_L<T, N>(p, sign, count, data, stride);
+  if (p.prec == FOCK_C64) {
+    using T = float;
+    switch (L) { FOCK_DFT_F32(CASE) default: break; }
+  } else {
+    using T = double;
+    switch (L) { FOCK_DFT_F64(CASE) default: break; }
+  }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+void prepare_reg_dft_kernels(fock_precision prec, int lim) {
+#define CASE(N) dft_reg_lds_attr<float, N>(lim);
+  if (prec == FOCK_C64) { FOCK_DFT_F32(CASE) }
+#undef CASE
+#define CASE(N) dft_reg_lds_attr<double, N>(lim);
+  if (prec == FOCK_C128) { FOCK_DFT_F64(CASE) }
 #undef CASE
 }
 

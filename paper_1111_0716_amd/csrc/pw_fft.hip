@@ -11,7 +11,9 @@
 //                  class of G, inverse DFT (unnormalised, exp(+))
 //   to the sphere  forward DFT in place, gather sqrt(Omega)/N F(class of G)
 //
-// DFT passes: per (grid, j1-plane) the axes 3 and 2 in LDS, per (grid,
+// DFT passes: on cubic grids with register-line kernels (pass_reg.hip) a
+// plane pass (axes 2 and 3, one line per lane) and a pencil pass (axis 1);
+// elsewhere per (grid, j1-plane) the axes 3 and 2 in LDS and per (grid,
 // c2-slab) the axis 1 in LDS (the LDS Stockham transforms of fft_lds.hpp),
 // so every {2,3,5}-smooth axis up to 72 works.
 #include <algorithm>
@@ -107,6 +109,12 @@ hipError_t dft3_t(const Plan& p, int inst, int sign, long long count, void* data
     const int nb = static_cast<int>(std::min<long long>(65535, count - b0));
     C* db = d + static_cast<size_t>(b0) * stride;
     p.prof.begin(FOCK_K_DFT, p.stream);
+    if (reg_dft_supported(p.prec, in.grid)) {
+      const hipError_t e = launch_reg_dft3(p, inst, sign, nb, db, stride);
+      p.prof.end(FOCK_K_DFT, p.stream);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     if (sign < 0) {
       hipLaunchKernelGGL((k_dft_planes<T, -1>), dim3(n1, nb), dim3(kBlock), lds_plane, p.stream, n2, n3, db, stride,
                          0LL, tw);
@@ -177,6 +185,7 @@ void dft_lds_attr(int lim) {
 }  // namespace
 
 void prepare_dft_kernels(fock_precision prec, int lim) {
+  prepare_reg_dft_kernels(prec, lim);
   if (prec == FOCK_C128)
     dft_lds_attr<double>(lim);
   else
