@@ -760,8 +760,8 @@ void dft_reg_lds_attr(int lim) {
 }
 
 // the lengths with one-lane DFT kernels, per precision (longer FP64 lines would spill)
-#define FOCK_DFT_F32(X) X(24) X(32) X(40) X(48) X(64) X(72)
-#define FOCK_DFT_F64(X) X(24) X(32)
+#define FOCK_DFT_F32(X) X(16) X(24) X(32) X(40) X(48) X(64) X(72)
+#define FOCK_DFT_F64(X) X(16) X(24) X(32)
 
 }  // namespace
 
@@ -793,7 +793,7 @@ void prepare_reg_kernels(fock_precision prec, int lim) {
 bool reg_dft_supported(fock_precision prec, const int grid[3]) {
   if (grid[0] != grid[1] || grid[0] != grid[2]) return false;
   switch (grid[0]) {
-    case 24: case 32: return true;
+    case 16: case 24: case 32: return true;
     case 40: case 48: case 64: case 72: return prec == FOCK_C64;
     default: return false;
   }
