@@ -51,8 +51,10 @@ def sources_sha256(kind):
     return h.hexdigest()
 
 
-def short_name(name):
-    """Kernel name without the argument list: `void ns::k<T, 32>(...)` -> `ns::k<T, 32>`."""
+def short_name(name, limit=100):
+    """Kernel name without the argument list: `void ns::k<T, 32>(...)` ->
+    `ns::k<T, 32>`; names longer than `limit` are cut (template arguments of
+    other libraries' kernels run to kilobytes)."""
     name = re.sub(r"^void ", "", name).replace("(anonymous namespace)::", "")
     depth = 0
     for i, ch in enumerate(name):
@@ -61,8 +63,9 @@ def short_name(name):
         elif ch == ">":
             depth -= 1
         elif ch == "(" and depth == 0:
-            return name[:i]
-    return name
+            name = name[:i]
+            break
+    return name if len(name) <= limit else name[:limit] + " ..."
 
 
 def _one(pattern):
