@@ -455,6 +455,65 @@ def pw(args):
     print(json.dumps(line), flush=True)
 
 
+def precision(args):
+    """Precision policies on the alpha-boron workload: which calls of a step
+    (apply, energy, backward) run on the FP32 path and which on the FP64
+    path, with the step time and the error of each result against the FP64
+    path (itself held to 1e-12 of the oracle by the parity tests)."""
+    import torch
+
+    from paper_1111_0716_amd import fock, inputs
+
+    device = torch.device("cuda:0")
+    inst = inputs.config("2", dtype=np.complex128, workers=16)
+    occ = torch.from_numpy(inst.occ).to(device)
+    psi = {"c64": torch.from_numpy(inst.psi.astype(np.complex64)).to(device),
+           "c128": torch.from_numpy(inst.psi).to(device)}
+    plans = {pr: fock.Plan([inst], precision=pr, device=device) for pr in ("c64", "c128")}
+    m = plans["c128"].meta[0]
+    scale = 2.0 * m["omega"] / m["npts"]
+    gex = torch.ones(1, dtype=torch.float64, device=device)
+    policies = {"all FP64": ("c128", "c128", "c128"), "all FP32": ("c64", "c64", "c64"),
+                "FP32 apply and backward, FP64 energy": ("c64", "c128", "c64")}
+    rows, ref = {}, None
+    for name, (pa, pe, pb) in list(policies.items()):
+        def step():
+            (vx,), _ = plans[pa].fock_apply([psi[pa]], [occ])
+            ex = plans[pe].fock_energy([psi[pe]], [occ])
+            (g,) = plans[pb].fock_energy_backward([psi[pb]], [occ], gex, scale)
+            return vx, ex, g
+        step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            vx, ex, g = step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        vx = vx.to(torch.complex128).cpu().numpy()
+        g = g.to(torch.complex128).cpu().numpy()
+        ex = float(ex.item())
+        if ref is None:
+            ref = (vx, ex, g)
+        rows[name] = {"calls": {"apply": pa, "energy": pe, "backward": pb}, "ms_per_step": round(ms, 3),
+                      "ex_rel_err": abs(ex - ref[1]) / abs(ref[1]),
+                      "vx_rel_err": float(np.linalg.norm(vx - ref[0]) / np.linalg.norm(ref[0])),
+                      "grad_rel_err": float(np.linalg.norm(g - ref[2]) / np.linalg.norm(ref[2]))}
+        log(f"  {name}: {ms:.1f} ms/step, E_x err {rows[name]['ex_rel_err']:.2e}, V_x err {rows[name]['vx_rel_err']:.2e}")
+    pairs = plans["c64"].stats()["ordered_pairs"]
+    best = rows["all FP32"]
+    line = {"metric": "precision policies: band-pair Fock applications/s and error vs the FP64 path",
+            "value": round(pairs / (best["ms_per_step"] / 1e3), 1),
+            "unit": "ordered band pairs/s (all-FP32 policy; apply + energy + backward)", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": best["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "c64 / c128 per call", "data": "synthetic",
+            "config": {"workload": WORKLOADS["2"]}, "policies": rows}
+    for p in plans.values():
+        p.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -464,7 +523,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw"], default="alpha")
+    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw", "precision"], default="alpha")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (the reference dispatch "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -480,6 +539,8 @@ def main():
         return fft3d(args)
     if args.workload == "pw":
         return pw(args)
+    if args.workload == "precision":
+        return precision(args)
 
     import torch
 
