@@ -50,7 +50,7 @@ struct RegShape {
   static constexpr int WPE_PENCIL = L <= 48 ? 2 : 1;
   static constexpr int WPE_ACC = 2 * LINE_REGS <= 160 ? 2 : 1;
   // operand batches: larger where the kernel has a whole SIMD's registers
-  static constexpr int PLANE_B = WPE_PLANE == 1 ? 24 : kRegB;
+  static constexpr int PLANE_B = kRegB;
   static constexpr int ACC_B = (WPE_ACC == 1 && sizeof(T) == 4) ? 16 : kRegB;
 };
 
@@ -65,30 +65,28 @@ __host__ __device__ constexpr int batch_of(int L, int want) {
   return b;
 }
 
-// x[j] = conj(b[j * stride]) a[j * stride], j < L, in batches of BW
+// x[j] = conj(b[j * stride]) a[j * stride], j < L: a straight into the line
+// (all loads in flight at once), then b in batches of BW multiplied in place,
+// so only one batch of operands is live beside the line
 template <typename C, int L, int BW = kRegB>
 __device__ __forceinline__ void load_codensity_line(C* x, const C* __restrict__ a, const C* __restrict__ b,
                                                     int stride) {
   constexpr int B = batch_of(L, BW);
   constexpr int NB = L / B;
-  C ab[2][B], bb[2][B];
 #pragma unroll
-  for (int j = 0; j < B; ++j) {
-    ab[0][j] = a[j * stride];
-    bb[0][j] = b[j * stride];
-  }
+  for (int j = 0; j < L; ++j) x[j] = a[j * stride];
+  C bb[2][B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) bb[0][j] = b[j * stride];
 #pragma unroll
   for (int n = 0; n < NB; ++n) {
     if (n + 1 < NB) {
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        ab[(n + 1) & 1][j] = a[((n + 1) * B + j) * stride];
-        bb[(n + 1) & 1][j] = b[((n + 1) * B + j) * stride];
-      }
+      for (int j = 0; j < B; ++j) bb[(n + 1) & 1][j] = b[((n + 1) * B + j) * stride];
     }
     reg_fence();
 #pragma unroll
-    for (int j = 0; j < B; ++j) x[n * B + j] = cmulconj(bb[n & 1][j], ab[n & 1][j]);
+    for (int j = 0; j < B; ++j) x[n * B + j] = cmulconj(bb[n & 1][j], x[n * B + j]);
   }
 }
 
