@@ -457,9 +457,9 @@ def pw(args):
 
 def precision(args):
     """Precision policies on the alpha-boron workload: which calls of a step
-    (apply, energy, backward) run on the FP32 path and which on the FP64
-    path, with the step time and the error of each result against the FP64
-    path (itself held to 1e-12 of the oracle by the parity tests)."""
+    (apply, energy, backward) run on the FP32, FP64 or mixed path, with the
+    step time and the error of each result against the FP64 path (itself
+    held to 1e-12 of the oracle by the parity tests)."""
     import torch
 
     from paper_1111_0716_amd import fock, inputs
@@ -469,12 +469,15 @@ def precision(args):
     occ = torch.from_numpy(inst.occ).to(device)
     psi = {"c64": torch.from_numpy(inst.psi.astype(np.complex64)).to(device),
            "c128": torch.from_numpy(inst.psi).to(device)}
-    plans = {pr: fock.Plan([inst], precision=pr, device=device) for pr in ("c64", "c128")}
+    psi["mixed"] = psi["c128"]
+    plans = {pr: fock.Plan([inst], precision=pr, device=device) for pr in ("c64", "c128", "mixed")}
     m = plans["c128"].meta[0]
     scale = 2.0 * m["omega"] / m["npts"]
     gex = torch.ones(1, dtype=torch.float64, device=device)
     policies = {"all FP64": ("c128", "c128", "c128"), "all FP32": ("c64", "c64", "c64"),
-                "FP32 apply and backward, FP64 energy": ("c64", "c128", "c64")}
+                "FP32 apply and backward, FP64 energy": ("c64", "c128", "c64"),
+                "mixed in every call (FP32 co-density and forward, FP64 multiply, inverse, accumulate)":
+                    ("mixed", "mixed", "mixed")}
     rows, ref = {}, None
     for name, (pa, pe, pb) in list(policies.items()):
         def step():

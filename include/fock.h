@@ -62,7 +62,13 @@ typedef enum {
   FOCK_ERR_STATE = 5        /* call out of order (e.g. apply before fock_set_workspace)           */
 } fock_status;
 
-typedef enum { FOCK_C128 = 0, FOCK_C64 = 1 } fock_precision;
+/* FOCK_C128: complex128 throughout.  FOCK_C64: complex64 orbitals, FP32
+ * arithmetic (FP64 tables, twiddles and energy sums).  FOCK_MIXED: complex128
+ * orbitals and outputs; co-densities and forward transforms in FP32, kernel
+ * multiply, inverse transforms and accumulate in FP64 (the paper's "some of
+ * the FFTs in single precision"); cubic grids of 24, 32, 40, 48, 64 or 72
+ * points only (FOCK_ERR_UNSUPPORTED otherwise). */
+typedef enum { FOCK_C128 = 0, FOCK_C64 = 1, FOCK_MIXED = 2 } fock_precision;
 
 /* One exchange problem ("instance").  All pointers are HOST pointers and are
  * only read during fock_plan. */

@@ -92,7 +92,9 @@ struct GraphCache {
 
 struct Plan {
   fock_precision prec;
-  size_t csize;  // sizeof(complex element)
+  size_t csize;  // sizeof(complex element) of orbitals and outputs
+  // orbitals, outputs and overlaps are complex128 (FOCK_C128 and FOCK_MIXED)
+  bool io64() const { return prec != FOCK_C64; }
   hipStream_t stream = nullptr;
   std::vector<Instance> inst;
   std::vector<Batch> apply_batches, energy_batches;
@@ -101,6 +103,7 @@ struct Plan {
   size_t tw_off = 0;                  // twiddle tables
   size_t const_bytes = 0;             // uploaded prefix
   size_t tbuf_off = 0, tbuf_bytes = 0;
+  size_t tbuf64_off = 0;  // FOCK_MIXED: FP64 pair buffer beside the FP32 one at tbuf_off
   size_t epart_off = 0, epart_bytes = 0;
   size_t ebsum_off = 0, ebsum_bytes = 0;
   size_t partial_off = 0, partial_bytes = 0;

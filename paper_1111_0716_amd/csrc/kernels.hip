@@ -388,7 +388,7 @@ hipError_t launch_zero_all_bands(const Plan& p, int inst, void* out) {
   for (int b0 = 0; b0 < nbt; b0 += 65535) {
     const int nb = std::min(65535, nbt - b0);
     p.prof.begin(FOCK_K_OTHER, p.stream);
-    if (p.prec == FOCK_C128) {
+    if (p.io64()) {
       hipLaunchKernelGGL((k_zero_bands<double>), dim3(gx, nb), dim3(kBlock), 0, p.stream, static_cast<double2*>(out),
                          b0, static_cast<long long>(in.band_stride), static_cast<long long>(in.npts));
     } else {
@@ -401,7 +401,7 @@ hipError_t launch_zero_all_bands(const Plan& p, int inst, void* out) {
 }
 
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out) {
-  return p.prec == FOCK_C128 ? zero_outputs_t<double>(p, inst, out) : zero_outputs_t<float>(p, inst, out);
+  return p.io64() ? zero_outputs_t<double>(p, inst, out) : zero_outputs_t<float>(p, inst, out);
 }
 
 hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
@@ -414,7 +414,7 @@ hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
   prepare_reg_kernels(prec, lim - 64);
   prepare_dft_kernels(prec, lim - 64);
   if (lim > 65536) {
-    if (prec == FOCK_C128)
+    if (prec != FOCK_C64)
       allow_large_lds<double>(lim - 64);
     else
       allow_large_lds<float>(lim - 64);
@@ -424,12 +424,12 @@ hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
 
 hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                               const double* gscale, double hscale, bool backward) {
-  return p.prec == FOCK_C128 ? apply_batch_t<double>(p, b, psi, occ, out, gscale, hscale, backward)
+  return p.io64() ? apply_batch_t<double>(p, b, psi, occ, out, gscale, hscale, backward)
                              : apply_batch_t<float>(p, b, psi, occ, out, gscale, hscale, backward);
 }
 
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
-  return p.prec == FOCK_C128 ? energy_batch_t<double>(p, b, psi, occ) : energy_batch_t<float>(p, b, psi, occ);
+  return p.io64() ? energy_batch_t<double>(p, b, psi, occ) : energy_batch_t<float>(p, b, psi, occ);
 }
 
 hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ, int n2) {

@@ -156,7 +156,7 @@ size_t overlap_scratch_bytes(const Instance& in) {
 }
 
 hipError_t launch_overlap(const Plan& p, int inst, const void* psi, const void* vx, void* vmat) {
-  return p.prec == FOCK_C128 ? overlap_t<double>(p, inst, psi, vx, vmat) : overlap_t<float>(p, inst, psi, vx, vmat);
+  return p.io64() ? overlap_t<double>(p, inst, psi, vx, vmat) : overlap_t<float>(p, inst, psi, vx, vmat);
 }
 
 }  // namespace fock

@@ -65,17 +65,26 @@ __host__ __device__ constexpr int batch_of(int L, int want) {
   return b;
 }
 
+// complex value in another precision
+template <typename C, typename CI>
+__device__ __forceinline__ C cvt(CI v) {
+  using T = decltype(C{}.x);
+  return C{static_cast<T>(v.x), static_cast<T>(v.y)};
+}
+
 // x[j] = conj(b[j * stride]) a[j * stride], j < L: a straight into the line
 // (all loads in flight at once), then b in batches of BW multiplied in place,
-// so only one batch of operands is live beside the line
-template <typename C, int L, int BW = kRegB>
-__device__ __forceinline__ void load_codensity_line(C* x, const C* __restrict__ a, const C* __restrict__ b,
+// so only one batch of operands is live beside the line.  The orbitals may
+// be stored in a wider precision (CI) than the line (C): they are rounded on
+// load.
+template <typename C, int L, int BW = kRegB, typename CI = C>
+__device__ __forceinline__ void load_codensity_line(C* x, const CI* __restrict__ a, const CI* __restrict__ b,
                                                     int stride) {
   constexpr int B = batch_of(L, BW);
   constexpr int NB = L / B;
 #pragma unroll
-  for (int j = 0; j < L; ++j) x[j] = a[j * stride];
-  C bb[2][B];
+  for (int j = 0; j < L; ++j) x[j] = cvt<C>(a[j * stride]);
+  CI bb[2][B];
 #pragma unroll
   for (int j = 0; j < B; ++j) bb[0][j] = b[j * stride];
 #pragma unroll
@@ -86,7 +95,7 @@ __device__ __forceinline__ void load_codensity_line(C* x, const C* __restrict__ 
     }
     reg_fence();
 #pragma unroll
-    for (int j = 0; j < B; ++j) x[n * B + j] = cmulconj(bb[n & 1][j], x[n * B + j]);
+    for (int j = 0; j < B; ++j) x[n * B + j] = cmulconj(cvt<C>(bb[n & 1][j]), x[n * B + j]);
   }
 }
 
@@ -133,9 +142,11 @@ __device__ __forceinline__ void transpose_plane(C* x, T* sp, int col) {
 // ---------------------------------------------------------------------------
 // plane pass: rho = conj(u_m) u_n, FFT along axes 2 and 3, T[j1][c3][c2]
 // ---------------------------------------------------------------------------
-template <typename T, int L, bool EXPLICIT>
-__global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE)) void k_plane_reg(
-    int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP,
+// (orbitals wider than the transform, FOCK_MIXED: one wave per SIMD, so the
+// wide operands fit beside the line without spilling)
+template <typename T, int L, bool EXPLICIT, typename TI = T>
+__global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? RegShape<T, L>::WPE_PLANE : 1)) void k_plane_reg(
+    int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP,
     const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
@@ -158,8 +169,9 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE))
   }
   C x[L];
   if (valid) {
-    load_codensity_line<C, L, Sh::PLANE_B>(x, psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col,
-                                           psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col, L);
+    load_codensity_line<C, L, Sh::PLANE_B, typename cx<TI>::t>(
+        x, psi + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col,
+        psi + static_cast<size_t>(pkm) * bs + static_cast<size_t>(j1) * LL + col, L);
   } else {
 #pragma unroll
     for (int j2 = 0; j2 < L; ++j2) x[j2] = C{T(0), T(0)};
@@ -204,10 +216,10 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_ap
 // ---------------------------------------------------------------------------
 // pencil pass, energy: FFT_1 and sum v_q/N |P|^2 in FP64 per line block
 // ---------------------------------------------------------------------------
-template <typename T, int L>
+template <typename T, int L, typename TV = T>
 __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_energy_reg(const PairRef* __restrict__ pairs,
                                                            const typename cx<T>::t* __restrict__ tbuf,
-                                                           const T* __restrict__ vtab, double* __restrict__ epart) {
+                                                           const TV* __restrict__ vtab, double* __restrict__ epart) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
@@ -222,7 +234,7 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_en
 #pragma unroll
     for (int j1 = 0; j1 < L; ++j1) x[j1] = base[static_cast<size_t>(j1) * LL];
     reg_fft<C, L, -1>(x);
-    const T* v = vtab + static_cast<size_t>(q) * LL * L + l;
+    const TV* v = vtab + static_cast<size_t>(q) * LL * L + l;
 #pragma unroll
     for (int c1 = 0; c1 < L; ++c1) {
       const double px = static_cast<double>(x[c1].x), py = static_cast<double>(x[c1].y);
@@ -479,9 +491,9 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_ap
   for (int m = 0; m < LH; ++m) base[static_cast<size_t>(2 * m) * LL] = y[m];
 }
 
-template <typename T, int L>
+template <typename T, int L, typename TV = T>
 __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_energy_split(
-    const PairRef* __restrict__ pairs, const typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab,
+    const PairRef* __restrict__ pairs, const typename cx<T>::t* __restrict__ tbuf, const TV* __restrict__ vtab,
     double* __restrict__ epart) {
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
@@ -498,7 +510,7 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_en
 #pragma unroll
     for (int m = 0; m < LH; ++m) y[m] = base[static_cast<size_t>(2 * m) * LL];
     split_fft_fwd<C, L>(y, h);
-    const T* v = vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l;
+    const TV* v = vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l;
 #pragma unroll
     for (int k = 0; k < LH; ++k) {
       const double px = static_cast<double>(y[k].x), py = static_cast<double>(y[k].y);
@@ -588,6 +600,41 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
 #pragma unroll
     for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cscale(acc[m], ft);
   }
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision (FOCK_MIXED): pencil pass from the FP32 pair buffer to the
+// FP64 one: forward axis 1 in FP32, kernel multiply and inverse in FP64
+// ---------------------------------------------------------------------------
+template <int L>
+__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int nbands, int nk, int o0, int nP,
+                                                               const int2* __restrict__ parts,
+                                                               const int* __restrict__ qmap,
+                                                               const float2* __restrict__ t32,
+                                                               double2* __restrict__ t64,
+                                                               const double* __restrict__ vtab) {
+  constexpr int LL = L * L, LH = L / 2, LPB = 128;
+  const int h = threadIdx.x & 1;
+  const int l = blockIdx.x * LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
+  const int pi = blockIdx.y;
+  if (l >= LL) return;  // uniform over the pair; no barrier in this kernel
+  const int o = pi / nP, p = pi - o * nP;
+  const int q = qmap[((o0 + o) / nbands) * nk + parts[p].x];
+  const size_t base = static_cast<size_t>(pi) * LL * L + static_cast<size_t>(h) * LL + l;
+  double2 y[LH];
+  {
+    float2 f[LH];
+#pragma unroll
+    for (int m = 0; m < LH; ++m) f[m] = t32[base + static_cast<size_t>(2 * m) * LL];  // j1 = 2m + h
+    split_fft_fwd<float2, L>(f, h);  // f[k] at c1 = h L/2 + k
+#pragma unroll
+    for (int k = 0; k < LH; ++k) y[k] = cvt<double2>(f[k]);
+  }
+  mul_table_line<double2, double, LH>(y, vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l,
+                                      LL);
+  split_fft_inv<double2, L>(y, h);
+#pragma unroll
+  for (int m = 0; m < LH; ++m) t64[base + static_cast<size_t>(2 * m) * LL] = y[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -712,8 +759,111 @@ void reg_lds_attr(int lim) {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
 
+// FOCK_MIXED: FP32 plane pass (FP64 orbitals rounded on load), mixed pencil
+// pass, FP64 accumulate pass (the FP64 variant of the length)
+template <int L>
+struct MixedPolicy {
+  using Acc = RegPolicy<double, L>;
+  static constexpr int PLANE_LDS = RegShape<float, L>::LDS;
+  static constexpr int LDS = PLANE_LDS > Acc::ACC_LDS ? PLANE_LDS : Acc::ACC_LDS;
+};
+
+template <int L>
+hipError_t mixed_apply_L(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                         const double* gscale, double hscale, bool backward) {
+  using Sh = RegShape<float, L>;
+  using Acc = RegPolicy<double, L>;
+  const Instance& in = p.inst[b.inst];
+  const long long bs = static_cast<long long>(in.band_stride);
+  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
+  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
+  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
+  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
+  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
+  double2* t64 = reinterpret_cast<double2*>(p.ws + p.tbuf64_off);
+  p.prof.begin(FOCK_K_PLANE, p.stream);
+  hipLaunchKernelGGL((k_plane_reg<float, L, false, double>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
+                     in.nbands, bs, static_cast<const double2*>(psi), b.o0, b.nP, parts,
+                     static_cast<const PairRef*>(nullptr), t32);
+  p.prof.end(FOCK_K_PLANE, p.stream);
+  p.prof.begin(FOCK_K_PENCIL, p.stream);
+  hipLaunchKernelGGL((k_pencil_apply_mixed<L>), dim3((L * L + 127) / 128, b.npairs), dim3(256), 0, p.stream, in.nbands,
+                     in.nk, b.o0, b.nP, parts, qmap, static_cast<const float2*>(t32), t64, vtab);
+  p.prof.end(FOCK_K_PENCIL, p.stream);
+  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
+  if constexpr (Acc::SPLIT_ACC) {
+    hipLaunchKernelGGL((k_acc_split<double, L>), dim3(Acc::ACC_NG, b.nO), dim3(Acc::ACC_NT), Acc::ACC_LDS, p.stream,
+                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const double2*>(t64),
+                       static_cast<const double2*>(psi), occ, kw, static_cast<double2*>(out), b.first, gscale, hscale,
+                       backward ? 1 : 0);
+  } else {
+    hipLaunchKernelGGL((k_acc_reg<double, L>), dim3(Acc::ACC_NG, b.nO), dim3(Acc::ACC_NT), Acc::ACC_LDS, p.stream,
+                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const double2*>(t64),
+                       static_cast<const double2*>(psi), occ, kw, static_cast<double2*>(out), b.first, gscale, hscale,
+                       backward ? 1 : 0);
+  }
+  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t mixed_energy_L(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+  using Sh = RegShape<float, L>;
+  using Po = RegPolicy<float, L>;
+  const Instance& in = p.inst[b.inst];
+  const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
+  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
+  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
+  double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
+  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
+  hipLaunchKernelGGL((k_plane_reg<float, L, true, double>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
+                     in.nbands, static_cast<long long>(in.band_stride), static_cast<const double2*>(psi), 0, 1,
+                     static_cast<const int2*>(nullptr), pairs, t32);
+  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
+  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
+  if constexpr (Po::SPLIT_PENCIL) {
+    hipLaunchKernelGGL((k_pencil_energy_split<float, L, double>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream,
+                       pairs, static_cast<const float2*>(t32), vtab, epart);
+  } else {
+    hipLaunchKernelGGL((k_pencil_energy_reg<float, L, double>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
+                       static_cast<const float2*>(t32), vtab, epart);
+  }
+  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
+  return launch_energy_reduce(p, b, occ, Po::NLB);
+}
+
+template <int L>
+void mixed_lds_attr(int lim) {
+  using Acc = RegPolicy<double, L>;
+  const void* fs[3] = {reinterpret_cast<const void*>(&k_plane_reg<float, L, false, double>),
+                       reinterpret_cast<const void*>(&k_plane_reg<float, L, true, double>), nullptr};
+  if constexpr (Acc::SPLIT_ACC)
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<double, L>);
+  else
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L>);
+  for (const void* f : fs)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+}
+
 // the cubic lengths with register-line kernels
 #define FOCK_REG_L(X) X(24) X(32) X(40) X(48) X(64) X(72)
+
+hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                         const double* gscale, double hscale, bool backward) {
+#define CASE(N) \
+  case N: return mixed_apply_L<N>(p, b, psi, occ, out, gscale, hscale, backward);
+  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t mixed_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+#define CASE(N) \
+  case N: return mixed_energy_L<N>(p, b, psi, occ);
+  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
+#undef CASE
+  return hipErrorInvalidValue;
+}
 
 template <typename T>
 hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
@@ -774,16 +924,21 @@ bool reg_supported(fock_precision prec, const int grid[3]) {
 
 size_t reg_lds_bytes(fock_precision prec, int L) {
   size_t r = 0;
-#define CASE(N) \
-  case N: r = prec == FOCK_C64 ? RegPolicy<float, N>::LDS : RegPolicy<double, N>::LDS; break;
+#define CASE(N)                                                                                \
+  case N:                                                                                      \
+    r = prec == FOCK_C64 ? RegPolicy<float, N>::LDS                                            \
+                         : (prec == FOCK_MIXED ? MixedPolicy<N>::LDS : RegPolicy<double, N>::LDS); \
+    break;
   switch (L) { FOCK_REG_L(CASE) default: break; }
 #undef CASE
   return r;
 }
 
 void prepare_reg_kernels(fock_precision prec, int lim) {
-#define CASE(N) \
-  if (prec == FOCK_C64) reg_lds_attr<float, N>(lim); else reg_lds_attr<double, N>(lim);
+#define CASE(N)                                     \
+  if (prec == FOCK_C64) reg_lds_attr<float, N>(lim); \
+  else if (prec == FOCK_MIXED) mixed_lds_attr<N>(lim); \
+  else reg_lds_attr<double, N>(lim);
   FOCK_REG_L(CASE)
 #undef CASE
 }
@@ -817,17 +972,19 @@ void prepare_reg_dft_kernels(fock_precision prec, int lim) {
   if (prec == FOCK_C64) { FOCK_DFT_F32(CASE) }
 #undef CASE
 #define CASE(N) dft_reg_lds_attr<double, N>(lim);
-  if (prec == FOCK_C128) { FOCK_DFT_F64(CASE) }
+  if (prec != FOCK_C64) { FOCK_DFT_F64(CASE) }
 #undef CASE
 }
 
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                                   const double* gscale, double hscale, bool backward) {
+  if (p.prec == FOCK_MIXED) return mixed_apply_t(p, b, psi, occ, out, gscale, hscale, backward);
   return p.prec == FOCK_C128 ? reg_apply_t<double>(p, b, psi, occ, out, gscale, hscale, backward)
                              : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward);
 }
 
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+  if (p.prec == FOCK_MIXED) return mixed_energy_t(p, b, psi, occ);
   return p.prec == FOCK_C128 ? reg_energy_t<double>(p, b, psi, occ) : reg_energy_t<float>(p, b, psi, occ);
 }
 

@@ -150,8 +150,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0};
   auto p = std::make_unique<Plan>();
   p->prec = prec;
-  p->csize = prec == FOCK_C128 ? 16 : 8;
-  const size_t rsize = prec == FOCK_C128 ? 8 : 4;
+  p->csize = prec == FOCK_C64 ? 8 : 16;
+  const size_t rsize = prec == FOCK_C64 ? 4 : 8;  // kernel tables: FP64 unless the whole path is FP32
   p->stream = static_cast<hipStream_t>(stream);
   p->inst.resize(n_inst);
 
@@ -216,8 +216,10 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const char* noreg = std::getenv("FOCK_NO_REG");
   const bool no_reg = noreg && *noreg && *noreg != '0';
   for (auto& in : p->inst) {
-    in.fused = fused_supported(prec, in.grid) && !no_fused;
+    in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
+    if (prec == FOCK_MIXED && !in.reg)
+      return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a cubic grid of 24, 32, 40, 48, 64 or 72 points");
   }
 
   // ---- batch shapes ----
@@ -368,7 +370,13 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->const_bytes = off;
   // ---- scratch ----
   p->tbuf_off = off;
-  p->tbuf_bytes = max_pairs_elems * p->csize;
+  if (prec == FOCK_MIXED) {
+    // FP32 pair buffer (plane pass out, pencil in), then the FP64 one
+    p->tbuf64_off = align_up(off + max_pairs_elems * 8);
+    p->tbuf_bytes = p->tbuf64_off - off + max_pairs_elems * 16;
+  } else {
+    p->tbuf_bytes = max_pairs_elems * p->csize;
+  }
   off = align_up(off + p->tbuf_bytes);
   p->epart_off = off;
   p->epart_bytes = std::max(max_epairs * max_n2, max_fused_epairs) * sizeof(double);
@@ -403,7 +411,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       // exp(-2 pi i t/L) in FP64, rounded once
       const double ang = -2.0 * M_PI * static_cast<double>(t) / static_cast<double>(L);
       const double c = std::cos(ang), s = std::sin(ang);
-      if (prec == FOCK_C128) {
+      if (prec != FOCK_C64) {
         double* w = reinterpret_cast<double*>(img + p->tw_off) + 2 * (o + t);
         w[0] = c;
         w[1] = s;
@@ -437,7 +445,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
               r[(static_cast<size_t>(c1) * L + c3) * L + c2] = t[(static_cast<size_t>(c1) * L + c2) * L + c3];
         t.swap(r);
       }
-      if (prec == FOCK_C128) {
+      if (prec != FOCK_C64) {
         std::memcpy(img + in.vtab_off + static_cast<size_t>(q) * in.npts * 8, t.data(), t.size() * 8);
       } else {
         float* dst = reinterpret_cast<float*>(img + in.vtab_off) + static_cast<size_t>(q) * in.npts;

@@ -186,26 +186,26 @@ void dft_lds_attr(int lim) {
 
 void prepare_dft_kernels(fock_precision prec, int lim) {
   prepare_reg_dft_kernels(prec, lim);
-  if (prec == FOCK_C128)
+  if (prec != FOCK_C64)
     dft_lds_attr<double>(lim);
   else
     dft_lds_attr<float>(lim);
 }
 
 hipError_t launch_dft3(const Plan& p, int inst, int sign, long long count, void* data, long long stride) {
-  return p.prec == FOCK_C128 ? dft3_t<double>(p, inst, sign, count, data, stride)
+  return p.io64() ? dft3_t<double>(p, inst, sign, count, data, stride)
                              : dft3_t<float>(p, inst, sign, count, data, stride);
 }
 
 hipError_t launch_pw_to_grid(const Plan& p, int inst, const void* coef, const int* gidx, const int* npw, int npw_max,
                              void* psi) {
-  return p.prec == FOCK_C128 ? pw_to_grid_t<double>(p, inst, coef, gidx, npw, npw_max, psi)
+  return p.io64() ? pw_to_grid_t<double>(p, inst, coef, gidx, npw, npw_max, psi)
                              : pw_to_grid_t<float>(p, inst, coef, gidx, npw, npw_max, psi);
 }
 
 hipError_t launch_grid_to_pw(const Plan& p, int inst, void* f, const int* gidx, const int* npw, int npw_max,
                              void* coef) {
-  return p.prec == FOCK_C128 ? grid_to_pw_t<double>(p, inst, f, gidx, npw, npw_max, coef)
+  return p.io64() ? grid_to_pw_t<double>(p, inst, f, gidx, npw, npw_max, coef)
                              : grid_to_pw_t<float>(p, inst, f, gidx, npw, npw_max, coef);
 }
 

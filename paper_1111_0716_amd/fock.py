@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfock.so")
 
 FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FOCK_ERR_STATE = range(6)
-FOCK_C128, FOCK_C64 = 0, 1
+FOCK_C128, FOCK_C64, FOCK_MIXED = 0, 1, 2
+PRECISIONS = {"c128": FOCK_C128, "c64": FOCK_C64, "mixed": FOCK_MIXED}
 
 EXPORTED = ["fock_plan", "fock_plan_tuned", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
             "fock_energy", "fock_energy_backward", "fock_pw_to_grid", "fock_grid_to_pw", "fock_apply_pw", "fock_dft3",
@@ -145,7 +146,9 @@ class Plan:
 
     ``instances``: objects with lattice, grid, kfrac, kweight, nbands, mu
     (e.g. paper_1111_0716_amd.inputs.Instance) or dicts with those keys.
-    ``precision``: "c64" (FP32 path) or "c128" (FP64 path)."""
+    ``precision``: "c64" (FP32 path), "c128" (FP64 path) or "mixed" (complex128
+    orbitals and outputs, FP32 co-densities and forward transforms, FP64 kernel
+    multiply, inverse transforms and accumulate; cubic 24-72 grids)."""
 
     def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None, tuning=None):
         import torch
@@ -154,7 +157,9 @@ class Plan:
         if not isinstance(instances, (list, tuple)):
             instances = [instances]
         self.precision = precision
-        self.prec = FOCK_C64 if precision == "c64" else FOCK_C128
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.prec = PRECISIONS[precision]
         self.cdtype = torch.complex64 if precision == "c64" else torch.complex128
         self.device = torch.device(device or "cuda:0")
         self.stream = stream

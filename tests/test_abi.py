@@ -144,3 +144,22 @@ def test_plan_counts_pairs():
     assert b.value == 36               # apply: one round trip per ordered pair
     assert c.value == (36 + 6) // 2    # energy: swapped pairs folded
     L.fock_destroy(h)
+
+
+def test_mixed_precision_plans_need_register_line_grids():
+    L = fock.lib()
+    keep = []
+    for grid, want in (((32, 32, 32), fock.FOCK_OK), ((72, 72, 72), fock.FOCK_OK), ((16, 16, 16), fock.FOCK_ERR_UNSUPPORTED),
+                       ((12, 10, 9), fock.FOCK_ERR_UNSUPPORTED)):
+        d = fock.make_desc(inputs.cubic_lattice(10.0), grid, np.zeros((1, 3)), nbands=2, keep=keep)
+        arr = (fock.FockDesc * 1)(d)
+        h = ctypes.c_void_p()
+        assert L.fock_plan(arr, 1, fock.FOCK_MIXED, None, ctypes.byref(h)) == want, grid
+        if want == fock.FOCK_OK:
+            size = ctypes.c_size_t()
+            assert L.fock_workspace_size(h, ctypes.byref(size)) == fock.FOCK_OK
+            L.fock_destroy(h)
+    d = fock.make_desc(inputs.cubic_lattice(10.0), (8, 8, 8), np.zeros((1, 3)), nbands=2, keep=keep)
+    arr = (fock.FockDesc * 1)(d)
+    h = ctypes.c_void_p()
+    assert L.fock_plan(arr, 1, 3, None, ctypes.byref(h)) == fock.FOCK_ERR_ARG

@@ -271,3 +271,36 @@ def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
     ee = abs(reg["ex"] - lds["ex"]) / abs(lds["ex"])
     log(f"  V_x {ev:.2e}  E_x {ee:.2e}")
     assert ev <= tol and ee <= tol
+
+
+@pytest.mark.parametrize("grid,kmesh,nb", [((24, 24, 24), (2, 1, 1), 3), ((32, 32, 32), (1, 2, 1), 2),
+                                           ((48, 48, 48), (1, 1, 1), 2), ((64, 64, 64), (1, 1, 1), 1),
+                                           ((72, 72, 72), (1, 1, 1), 1)])
+def test_mixed_precision_matches_oracle(grid, kmesh, nb, device):
+    """FP32 co-densities and forward transforms, FP64 multiply, inverse and
+    accumulate: complex128 in and out, held to the FP32 tolerances."""
+    log(f"mixed grid={grid} kmesh={kmesh} nb={nb}")
+    inst = inputs.small_instance(grid=grid, kmesh=kmesh, nbands=nb, seed=(209, grid[0]), full_grid=grid[0] == 32)
+    g = run_gpu(inst, "mixed", device, vmat=True)
+    o = Oracle.from_instance(inst)
+    vref, eref = o.apply(inst.psi, inst.occ)
+    ev = band_err(g["vx"], vref)
+    ee = abs(g["ex"] - eref) / abs(eref)
+    log(f"  V_x err {ev:.3e}  E_x err {ee:.3e}")
+    assert ev <= TOL["c64"]["v"] and ee <= TOL["c64"]["e"]
+    mref = o.overlap(inst.psi, vref)
+    assert np.max(np.abs(g["vmat"] - mref)) <= TOL["c64"]["v"] * np.max(np.abs(mref))
+
+
+def test_mixed_precision_backward(device):
+    import torch
+
+    inst = inputs.small_instance(grid=(24, 24, 24), kmesh=(2, 1, 1), nbands=3, seed=(210, 0), full_grid=True)
+    g = run_gpu(inst, "mixed", device)
+    plan, psi, occ = g["plan"], g["psi"], g["occ"]
+    o = Oracle.from_instance(inst)
+    gref = o.gradient(inst.psi, inst.occ)
+    gex = torch.full((1,), 0.5, dtype=torch.float64, device=device)
+    (gg,) = plan.fock_energy_backward([psi], [occ], gex, 2.0 * o.dv)
+    torch.cuda.synchronize()
+    assert band_err(gg.cpu().numpy(), 0.5 * gref) <= TOL["c64"]["v"]
