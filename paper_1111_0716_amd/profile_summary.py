@@ -12,6 +12,12 @@
       the factor that makes the same counter read B bytes on the largest plain
       device-to-device copy (`__amd_rocclr_copyBuffer`) of the same run.
 
+  python -m paper_1111_0716_amd.profile_summary counters DIR [DIR ...]
+         --kernel SUBSTR --title T --command C [--command C2 ...] [--out FILE]
+      every counter of the kernel whose name contains SUBSTR (mean over its
+      dispatches after the first) from one or more `--pmc` runs, with the
+      derived shares of wave time (VALU, LDS, waits) and the L2 hit rate
+
 The traffic summary carries machine-readable lines (`key: value`) that
 bench.py reads back; `sources_sha256` fingerprints the kernel's source files
 so that a later change of the kernel voids the figure.
@@ -142,6 +148,49 @@ def traffic_summary(a, argv):
     return "\n".join(lines)
 
 
+def read_all_counters(d, kernel):
+    """{counter: [values per dispatch of the kernel]} of one --pmc run."""
+    out = {}
+    with open(_one(os.path.join(d, "**", "*counter_collection.csv"))) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Dispatch_Id"]))
+    for r in rows:
+        if kernel in r["Kernel_Name"]:
+            out.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def counters_summary(dirs, kernel, title, commands):
+    vals = {}
+    for d in dirs:
+        for name, v in read_all_counters(d, kernel).items():
+            use = v[1:] if len(v) > 1 else v
+            vals[name] = sum(use) / len(use)
+    if not vals:
+        raise SystemExit(f"no dispatch of a kernel containing {kernel!r}")
+    lines = [f"# Counters: {title}", "", "Commands (from the repository root; one counter set per run):", "", "```",
+             *commands, "```", "", f"Kernel: `{kernel}`; mean over its dispatches after the first.", "",
+             "| counter | value per dispatch |", "|---|---|"]
+    lines += [f"| {k} | {v:.4e} |" for k, v in sorted(vals.items())]
+    derived = []
+    wc = vals.get("SQ_WAVE_CYCLES")
+    if wc:
+        for k, label in (("SQ_ACTIVE_INST_VALU", "VALU issuing"), ("SQ_ACTIVE_INST_LDS", "LDS issuing"),
+                         ("SQ_WAIT_INST_ANY", "waiting on s_waitcnt"), ("SQ_WAIT_INST_LDS", "waiting on LDS"),
+                         ("SQ_WAIT_ANY", "waiting (any)")):
+            if k in vals:
+                derived.append(f"- {label}: {100.0 * vals[k] / wc:.1f} % of wave cycles")
+    if "TCC_HIT_sum" in vals and "TCC_MISS_sum" in vals:
+        tot = vals["TCC_HIT_sum"] + vals["TCC_MISS_sum"]
+        if tot > 0:
+            derived.append(f"- L2 hit rate: {100.0 * vals['TCC_HIT_sum'] / tot:.1f} %")
+    if "SQ_LDS_BANK_CONFLICT" in vals and "SQ_INSTS_LDS" in vals:
+        derived.append(f"- LDS bank-conflict cycles per LDS instruction: "
+                       f"{vals['SQ_LDS_BANK_CONFLICT'] / max(vals['SQ_INSTS_LDS'], 1.0):.3f}")
+    if derived:
+        lines += ["", "Derived:", "", *derived]
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path, kind):
     """Scaled HBM bytes per launch from a traffic summary, or None when the
     file is absent or the kernel's sources changed since it was taken."""
@@ -174,9 +223,20 @@ def main(argv=None):
     c.add_argument("--title", required=True)
     c.add_argument("--command", action="append", required=True)
     c.add_argument("--out")
+    k = sub.add_parser("counters")
+    k.add_argument("dirs", nargs="+")
+    k.add_argument("--kernel", required=True)
+    k.add_argument("--title", required=True)
+    k.add_argument("--command", action="append", required=True)
+    k.add_argument("--out")
     argv = sys.argv[1:] if argv is None else list(argv)
     a = ap.parse_args(argv)
-    text = trace_summary(a.dir, a.title, a.command) if a.mode == "trace" else traffic_summary(a, argv)
+    if a.mode == "trace":
+        text = trace_summary(a.dir, a.title, a.command)
+    elif a.mode == "traffic":
+        text = traffic_summary(a, argv)
+    else:
+        text = counters_summary(a.dirs, a.kernel, a.title, a.command)
     if a.out:
         with open(a.out, "w") as f:
             f.write(text)

@@ -43,3 +43,15 @@ def test_traffic_calibration_and_fingerprint(tmp_path):
     out.write_text(text)
     assert ps.read_traffic(str(out), "fused") is None
     assert ps.read_traffic(str(tmp_path / "absent.md"), "fused") is None
+
+
+def test_counter_summary_means_and_derived_shares(tmp_path):
+    kern = "void fock::k_pair_fused<float, 32>(int)"
+    _write(str(tmp_path / "a"), "SQ_WAVE_CYCLES", [(kern, 10.0), (kern, 1000.0), (kern, 3000.0)])
+    d = str(tmp_path / "a" / "p_counter_collection.csv")
+    with open(d, "a") as f:
+        for i, v in enumerate((5.0, 500.0, 1500.0)):
+            f.write(f'{10 + i},{10 + i},"Agent 1",1,1,1,64,1,"{kern}",64,0,0,8,0,8,"SQ_ACTIVE_INST_VALU",{v},0,1\n')
+    text = ps.counters_summary([str(tmp_path / "a")], "k_pair_fused<float, 32>", "t", ["c"])
+    assert "| SQ_WAVE_CYCLES | 2.0000e+03 |" in text
+    assert "VALU issuing: 50.0 % of wave cycles" in text
