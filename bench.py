@@ -105,6 +105,9 @@ def roofline(kern, stats, grid, s, peak_tflops, traffic_file=None):
     if traffic_file:
         from paper_1111_0716_amd.profile_summary import read_traffic
         traffic = read_traffic(os.path.join(ROOT, traffic_file.format(kind=dom)), dom)
+    if traffic:
+        roof["traffic_gbs"] = round(traffic / (per_launch_ms * 1e-3) / 1e9, 1)
+        roof["traffic_over_algorithmic"] = round(traffic / byts, 4)
     roof.update({"traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                  "copy-calibrated)", "algorithmic_bytes_per_launch": byts, "kernel": dom, "launches": launches, "launch_ms": round(per_launch_ms, 4),
                  "units_per_launch": round(units[dom] / launches, 1),
