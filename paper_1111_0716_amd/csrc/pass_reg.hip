@@ -46,7 +46,7 @@ struct RegShape {
   // two where the line (and the accumulator) leave room for the transform
   // without spilling, as measured on the compiled kernels
   static constexpr int LINE_REGS = L * static_cast<int>(sizeof(C)) / 4;
-  static constexpr int WPE_PLANE = L <= 64 ? 2 : 1;
+  static constexpr int WPE_PLANE = 2;
   static constexpr int WPE_PENCIL = L <= 48 ? 2 : 1;
   static constexpr int WPE_ACC = 2 * LINE_REGS <= 160 ? 2 : 1;
   // operand batches: larger where the kernel has a whole SIMD's registers
