@@ -146,11 +146,14 @@ class Plan:
 
     ``instances``: objects with lattice, grid, kfrac, kweight, nbands, mu
     (e.g. paper_1111_0716_amd.inputs.Instance) or dicts with those keys.
+    ``band_stride``: per instance, elements between bands (default N): grid
+    tensors are then [nk, nbands, band_stride] with the grid in the first N.
     ``precision``: "c64" (FP32 path), "c128" (FP64 path) or "mixed" (complex128
     orbitals and outputs, FP32 co-densities and forward transforms, FP64 kernel
     multiply, inverse transforms and accumulate; cubic 24-72 grids)."""
 
-    def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None, tuning=None):
+    def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None, tuning=None,
+                 band_stride=None):
         import torch
 
         self.torch = torch
@@ -170,11 +173,13 @@ class Plan:
             g = _get(inst, "grid")
             nb = _get(inst, "nbands")
             kp = kpairs[i] if kpairs is not None else _get(inst, "kpairs", None)
+            bstride = band_stride[i] if band_stride is not None else None
             descs[i] = make_desc(_get(inst, "lattice"), g, _get(inst, "kfrac"), _get(inst, "kweight", None), nb,
-                                 None, _get(inst, "mu", 0.106), kp, keep)
+                                 bstride, _get(inst, "mu", 0.106), kp, keep)
             lat = np.asarray(_get(inst, "lattice"), dtype=np.float64).reshape(3, 3)
             n = int(np.prod(g))
-            self.meta.append(dict(nk=descs[i].nk, nbands=nb, npts=n, omega=abs(float(np.linalg.det(lat)))))
+            self.meta.append(dict(nk=descs[i].nk, nbands=nb, npts=n, omega=abs(float(np.linalg.det(lat))),
+                                  band_stride=int(descs[i].band_stride)))
         handle = c_void_p()
         self.tuning = dict(tuning) if tuning else {}
         tn = FockTuning(**{k: int(v) for k, v in self.tuning.items()}) if tuning else None
@@ -200,8 +205,9 @@ class Plan:
         t = self.torch
         if not (psi.is_cuda and psi.dtype == self.cdtype and psi.is_contiguous()):
             raise ValueError(f"psi[{i}] must be a contiguous {self.cdtype} CUDA tensor")
-        if tuple(psi.shape[:2]) != (m["nk"], m["nbands"]) or psi[0, 0].numel() != m["npts"]:
-            raise ValueError(f"psi[{i}] has shape {tuple(psi.shape)}, expected ({m['nk']}, {m['nbands']}, {m['npts']})")
+        if tuple(psi.shape[:2]) != (m["nk"], m["nbands"]) or psi[0, 0].numel() != m["band_stride"]:
+            raise ValueError(f"psi[{i}] has shape {tuple(psi.shape)}, expected "
+                             f"({m['nk']}, {m['nbands']}, {m['band_stride']})")
 
     def _check_occ(self, occ, i):
         m = self.meta[i]
@@ -278,7 +284,7 @@ class Plan:
         gidx, npw, npw_max = self._sphere(gidx, npw)
         for i, c in enumerate(coef):
             self._check_coef(c, i, npw_max[i])
-        out = [self.torch.empty((m["nk"], m["nbands"], m["npts"]), dtype=self.cdtype, device=self.device)
+        out = [self.torch.zeros((m["nk"], m["nbands"], m["band_stride"]), dtype=self.cdtype, device=self.device)
                for m in self.meta] if out is None else _aslist(out)
         for i, o in enumerate(out):
             self._check_psi(o, i)
@@ -312,7 +318,8 @@ class Plan:
             self._check_occ(o, i)
 
         def grids():
-            return [t.empty((m["nk"], m["nbands"], m["npts"]), dtype=self.cdtype, device=self.device) for m in self.meta]
+            return [t.zeros((m["nk"], m["nbands"], m["band_stride"]), dtype=self.cdtype, device=self.device)
+                    for m in self.meta]
 
         psi_work = grids() if psi_work is None else _aslist(psi_work)
         vx_work = grids() if vx_work is None else _aslist(vx_work)
