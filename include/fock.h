@@ -66,8 +66,8 @@ typedef enum {
  * arithmetic (FP64 tables, twiddles and energy sums).  FOCK_MIXED: complex128
  * orbitals and outputs; co-densities and forward transforms in FP32, kernel
  * multiply, inverse transforms and accumulate in FP64 (the paper's "some of
- * the FFTs in single precision"); cubic grids of 24, 32, 40, 48, 64 or 72
- * points only (FOCK_ERR_UNSUPPORTED otherwise). */
+ * the FFTs in single precision"); grids N1 x L x L with N1 and L each 24,
+ * 32, 40, 48, 64 or 72 only (FOCK_ERR_UNSUPPORTED otherwise). */
 typedef enum { FOCK_C128 = 0, FOCK_C64 = 1, FOCK_MIXED = 2 } fock_precision;
 
 /* One exchange problem ("instance").  All pointers are HOST pointers and are

@@ -54,7 +54,7 @@ struct Instance {
   std::vector<std::vector<int>> kpartners;  // k -> list of k'
   bool symmetric = true;                     // (k, k') listed iff (k', k) listed
   bool fused = false;                        // whole-pair path (cubic grid that fits one CU)
-  bool reg = false;                          // three-pass path with register-line kernels (cubic)
+  bool reg = false;                          // three-pass path with register-line kernels (N1 x L x L)
   int nbands;
   int64_t band_stride;
   double mu;

@@ -1,6 +1,7 @@
-// Three-pass kernels with register-line FFTs for cubic grids L^3 that do not
-// take the whole-pair kernels, L in {24, 32, 40, 48, 64, 72}: a line per lane
-// (FP32 L <= 48, FP64 L <= 32) or a line per lane pair (larger L).  Same passes and batching as the LDS-Stockham kernels (paper,
+// Three-pass kernels with register-line FFTs for grids N1 x L x L that do not
+// take the whole-pair kernels, N1 and L in {24, 32, 40, 48, 64, 72}: a line
+// per lane (FP32 up to 48, FP64 up to 32) or a line per lane pair (longer
+// lines).  Same passes and batching as the LDS-Stockham kernels (paper,
 // "Our Implementation": the band-pair loop on the GPU; NSIM-like blocks of
 // outputs x partners), but every 1-D transform runs in one thread's registers
 // on a whole line (reg_fft.hpp), a plane switches axes through one padded LDS
@@ -14,6 +15,10 @@
 //   acc     thread (p, c2): row of T -> IFFT_3 -> LDS -> thread (p, j3):
 //           column -> IFFT_2 -> acc += -w' f' u_m W in registers, for every
 //           partner of the batch; one write (or add) of the output per batch
+//
+// The plane and accumulate passes are compiled for the plane side L and take
+// the plane count N1 at run time; the pencil pass is compiled for the line
+// length N1 and takes the line count L^2 at run time.
 #include <algorithm>
 
 #include "fft_lds.hpp"
@@ -38,10 +43,7 @@ struct RegShape {
   static constexpr int PL0 = (256 / L) > 0 ? (256 / L) : 1;
   static constexpr int PL = (PL0 * PLANE_LDS <= 78 * 1024) ? PL0 : ((78 * 1024) / PLANE_LDS > 0 ? (78 * 1024) / PLANE_LDS : 1);
   static constexpr int NTP = PL * L;             // threads of the plane and accumulate passes
-  static constexpr int NG = (L + PL - 1) / PL;   // plane groups
   static constexpr int LDS = PL * PLANE_LDS;
-  static constexpr int NTL = 256;                // threads of the pencil pass (one line each)
-  static constexpr int NLB = (L * L + NTL - 1) / NTL;  // line blocks per pair
   // waves per SIMD each kernel is compiled for (register budget 512 / WPE):
   // two where the line (and the accumulator) leave room for the transform
   // without spilling, as measured on the compiled kernels
@@ -119,6 +121,42 @@ __device__ __forceinline__ void mul_table_line(C* x, const T* __restrict__ v, si
   }
 }
 
+// Pencil lines with the line count known only at run time: the address of
+// element j is a wave-uniform base (scalar registers) plus the lane's 32-bit
+// byte offset, so the loads of a line take no 64-bit address per element.
+template <typename C>
+__device__ __forceinline__ C* lane_at(C* u, unsigned o) {
+  return reinterpret_cast<C*>(reinterpret_cast<uintptr_t>(u) + o);
+}
+
+// v, through an empty asm the compiler cannot see through: addresses built
+// from the copy are formed where they are used instead of being kept live
+// (two registers each) across the transform in between
+__device__ __forceinline__ unsigned opaque(unsigned v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// x[j] *= u[j * stride] at the lane's byte offset o, j < L (u wave-uniform)
+template <typename C, typename T, int L>
+__device__ __forceinline__ void mul_table_line_u(C* x, const T* __restrict__ u, unsigned o, size_t stride) {
+  constexpr int B = batch_of(L, kRegB);
+  constexpr int NB = L / B;
+  T vb[2][B];
+#pragma unroll
+  for (int j = 0; j < B; ++j) vb[0][j] = *lane_at(u + j * stride, o);
+#pragma unroll
+  for (int n = 0; n < NB; ++n) {
+    if (n + 1 < NB) {
+#pragma unroll
+      for (int j = 0; j < B; ++j) vb[(n + 1) & 1][j] = *lane_at(u + ((n + 1) * B + j) * stride, o);
+    }
+    reg_fence();
+#pragma unroll
+    for (int j = 0; j < B; ++j) x[n * B + j] = cscale(x[n * B + j], vb[n & 1][j]);
+  }
+}
+
 // Switch a plane's axis: thread `col` holds line x[i] = P[i][col]; afterwards
 // it holds x[i] = P[col][i].  One component at a time through sp ([L][LP]
 // of T, this plane's share of LDS); every thread of the block must call it.
@@ -146,7 +184,7 @@ __device__ __forceinline__ void transpose_plane(C* x, T* sp, int col) {
 // wide operands fit beside the line without spilling)
 template <typename T, int L, bool EXPLICIT, typename TI = T>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? RegShape<T, L>::WPE_PLANE : 1)) void k_plane_reg(
-    int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP,
+    int n1, int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP,
     const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
@@ -154,7 +192,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? R
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int j1 = blockIdx.x * Sh::PL + pl;
-  const bool valid = j1 < L;
+  const bool valid = j1 < n1;
   const int pi = blockIdx.y;
   int okn, pkm;
   if (EXPLICIT) {
@@ -180,9 +218,18 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? R
   transpose_plane<C, T, L>(x, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col);  // now c2 = col
   reg_fft<C, L, -1>(x);  // axis 3: x[c3]
   if (valid) {
-    C* dst = tbuf + (static_cast<size_t>(pi) * L + j1) * LL + col;
+    if constexpr (sizeof(TI) != sizeof(T)) {
+      // wide orbitals: addresses formed at the stores (the form with the
+      // fewest registers for these variants, by the compiled kernels)
+      C* dst = tbuf + static_cast<size_t>(pi) * n1 * LL;
+      const unsigned so = opaque((static_cast<unsigned>(j1) * LL + col) * sizeof(C));
 #pragma unroll
-    for (int c3 = 0; c3 < L; ++c3) dst[c3 * L] = x[c3];
+      for (int c3 = 0; c3 < L; ++c3) *lane_at(dst + c3 * L, so) = x[c3];
+    } else {
+      C* dst = tbuf + (static_cast<size_t>(pi) * n1 + j1) * LL + col;
+#pragma unroll
+      for (int c3 = 0; c3 < L; ++c3) dst[c3 * L] = x[c3];
+    }
   }
 }
 
@@ -190,62 +237,65 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? R
 // pencil pass, apply: FFT_1, x v_q/N, IFFT_1 on lines (c3, c2) of T
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_apply_reg(int nbands, int nk, int o0, int nP,
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_apply_reg(int ll, int nbands, int nk, int o0, int nP,
                                                           const int2* __restrict__ parts, const int* __restrict__ qmap,
                                                           typename cx<T>::t* __restrict__ tbuf,
                                                           const T* __restrict__ vtab) {
   using C = typename cx<T>::t;
-  constexpr int LL = L * L;
+  const int LL = ll;  // lines per pair (N2 N3); L is the line length N1
   const int l = blockIdx.x * 256 + threadIdx.x;  // line (c3, c2) = l
   const int pi = blockIdx.y;
   if (l >= LL) return;  // no barrier in this kernel
   const int o = pi / nP, p = pi - o * nP;
   const int ok = (o0 + o) / nbands;
   const int q = qmap[ok * nk + parts[p].x];
-  C* base = tbuf + static_cast<size_t>(pi) * LL * L + l;
+  C* base = tbuf + static_cast<size_t>(pi) * LL * L;
+  const unsigned lo = static_cast<unsigned>(l) * sizeof(C);
   C x[L];
 #pragma unroll
-  for (int j1 = 0; j1 < L; ++j1) x[j1] = base[static_cast<size_t>(j1) * LL];
+  for (int j1 = 0; j1 < L; ++j1) x[j1] = *lane_at(base + static_cast<size_t>(j1) * LL, lo);
   reg_fft<C, L, -1>(x);
-  mul_table_line<C, T, L>(x, vtab + static_cast<size_t>(q) * LL * L + l, LL);
+  mul_table_line_u<C, T, L>(x, vtab + static_cast<size_t>(q) * LL * L, opaque(static_cast<unsigned>(l) * sizeof(T)), LL);
   reg_fft<C, L, +1>(x);
+  const unsigned so = opaque(lo);
 #pragma unroll
-  for (int j1 = 0; j1 < L; ++j1) base[static_cast<size_t>(j1) * LL] = x[j1];
+  for (int j1 = 0; j1 < L; ++j1) *lane_at(base + static_cast<size_t>(j1) * LL, so) = x[j1];
 }
 
 // ---------------------------------------------------------------------------
 // pencil pass, energy: FFT_1 and sum v_q/N |P|^2 in FP64 per line block
 // ---------------------------------------------------------------------------
 template <typename T, int L, typename TV = T>
-__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_energy_reg(const PairRef* __restrict__ pairs,
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_energy_reg(int ll, const PairRef* __restrict__ pairs,
                                                            const typename cx<T>::t* __restrict__ tbuf,
                                                            const TV* __restrict__ vtab, double* __restrict__ epart) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
-  constexpr int LL = L * L;
+  const int LL = ll;
   __shared__ double red[4];
   const int l = blockIdx.x * 256 + threadIdx.x;
   const int pi = blockIdx.y;
   double e = 0.0;
   if (l < LL) {
     const int q = pairs[pi].q;
-    const C* base = tbuf + static_cast<size_t>(pi) * LL * L + l;
+    const C* base = tbuf + static_cast<size_t>(pi) * LL * L;
     C x[L];
 #pragma unroll
-    for (int j1 = 0; j1 < L; ++j1) x[j1] = base[static_cast<size_t>(j1) * LL];
+    for (int j1 = 0; j1 < L; ++j1) x[j1] = *lane_at(base + static_cast<size_t>(j1) * LL, static_cast<unsigned>(l) * sizeof(C));
     reg_fft<C, L, -1>(x);
-    const TV* v = vtab + static_cast<size_t>(q) * LL * L + l;
+    const TV* v = vtab + static_cast<size_t>(q) * LL * L;
+    const unsigned lv = opaque(static_cast<unsigned>(l) * sizeof(TV));
 #pragma unroll
     for (int c1 = 0; c1 < L; ++c1) {
       const double px = static_cast<double>(x[c1].x), py = static_cast<double>(x[c1].y);
-      e += static_cast<double>(v[static_cast<size_t>(c1) * LL]) * (px * px + py * py);
+      e += static_cast<double>(*lane_at(v + static_cast<size_t>(c1) * LL, lv)) * (px * px + py * py);
     }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
   __syncthreads();
-  if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * Sh::NLB + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 // ---------------------------------------------------------------------------
@@ -253,7 +303,7 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_en
 // ---------------------------------------------------------------------------
 template <typename T, int L>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) void k_acc_reg(
-    int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
+    int n1, int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
     const double* __restrict__ gscale, double hscale, int backward) {
@@ -266,7 +316,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   T* sp = reinterpret_cast<T*>(smem_raw);
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int j1 = blockIdx.x * Sh::PL + pl;
-  const bool valid = j1 < L;
+  const bool valid = j1 < n1;
   const int o = blockIdx.y;
   sp += pl * L * Sh::LP;
   C acc[L];
@@ -276,7 +326,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
     const int2 r = parts[p];
     C x[L];
     if (valid) {
-      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * L + static_cast<size_t>(j1) * LL + col;
+      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * n1 + static_cast<size_t>(j1) * LL + col;
 #pragma unroll
       for (int c3 = 0; c3 < L; ++c3) x[c3] = src[c3 * L];  // row (j1, c2 = col)
     } else {
@@ -336,14 +386,14 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
 // line per lane, coalesced); two transposes bring the rows in and back out
 template <typename T, int L, int S>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE)) void k_dft_plane_reg(
-    typename cx<T>::t* __restrict__ data, long long stride) {
+    int n1, typename cx<T>::t* __restrict__ data, long long stride) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int j1 = blockIdx.x * Sh::PL + pl;
-  const bool valid = j1 < L;
+  const bool valid = j1 < n1;
   T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
   C* g = data + static_cast<size_t>(blockIdx.y) * stride + static_cast<size_t>(j1) * LL + col;
   C x[L];
@@ -362,18 +412,20 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE))
 // pencil pass: axis 1 of line (c2, c3) = l, coalesced across lanes
 template <typename T, int L, int S>
 __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_dft_pencil_reg(
-    typename cx<T>::t* __restrict__ data, long long stride) {
+    int ll, typename cx<T>::t* __restrict__ data, long long stride) {
   using C = typename cx<T>::t;
-  constexpr int LL = L * L;
+  const int LL = ll;
   const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= LL) return;  // no barrier in this kernel
-  C* g = data + static_cast<size_t>(blockIdx.y) * stride + l;
+  C* g = data + static_cast<size_t>(blockIdx.y) * stride;
+  const unsigned lo = static_cast<unsigned>(l) * sizeof(C);
   C x[L];
 #pragma unroll
-  for (int j1 = 0; j1 < L; ++j1) x[j1] = g[static_cast<size_t>(j1) * LL];
+  for (int j1 = 0; j1 < L; ++j1) x[j1] = *lane_at(g + static_cast<size_t>(j1) * LL, lo);
   reg_fft<C, L, S>(x);
+  const unsigned so = opaque(lo);
 #pragma unroll
-  for (int c1 = 0; c1 < L; ++c1) g[static_cast<size_t>(c1) * LL] = x[c1];
+  for (int c1 = 0; c1 < L; ++c1) *lane_at(g + static_cast<size_t>(c1) * LL, so) = x[c1];
 }
 
 // ---------------------------------------------------------------------------
@@ -397,10 +449,8 @@ struct SplitShape {
   static constexpr int TMAX = 2 * HALF_REGS > 160 ? 256 : 320;
   static constexpr int PL = (TMAX / TPP) > 0 ? (TMAX / TPP) : 1;
   static constexpr int NTP = PL * TPP;
-  static constexpr int NG = (L + PL - 1) / PL;
   static constexpr int LDS = PL * PLANE_LDS;
   static constexpr int LPB = 128;  // lines per pencil block
-  static constexpr int NLB = (L * L + LPB - 1) / LPB;
   static constexpr int WPE_LINE = HALF_REGS <= 64 ? 3 : (HALF_REGS <= 72 ? 2 : 1);
   static constexpr int WPE_ACC = 2 * HALF_REGS <= 144 ? 2 : 1;
 };
@@ -427,7 +477,7 @@ __device__ __forceinline__ void transpose_split(C* y, T* sp, int col, int h) {
 
 template <typename T, int L, bool EXPLICIT>
 __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LINE)) void k_plane_split(
-    int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP,
+    int n1, int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP,
     const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
@@ -435,7 +485,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LIN
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
   const int j1 = blockIdx.x * Sh::PL + pl;
-  const bool valid = j1 < L;
+  const bool valid = j1 < n1;
   const int pi = blockIdx.y;
   int okn, pkm;
   if (EXPLICIT) {
@@ -461,7 +511,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LIN
   transpose_split<C, T, L, false>(y, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col, h);  // c2 = col
   split_fft_fwd<C, L>(y, h);  // axis 3: y[k] at c3 = h L/2 + k
   if (valid) {
-    C* dst = tbuf + (static_cast<size_t>(pi) * L + j1) * LL + static_cast<size_t>(h) * LH * L + col;
+    C* dst = tbuf + (static_cast<size_t>(pi) * n1 + j1) * LL + static_cast<size_t>(h) * LH * L + col;
 #pragma unroll
     for (int k = 0; k < LH; ++k) dst[k * L] = y[k];
   }
@@ -469,35 +519,40 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LIN
 
 template <typename T, int L>
 __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_apply_split(
-    int nbands, int nk, int o0, int nP, const int2* __restrict__ parts, const int* __restrict__ qmap,
+    int ll, int nbands, int nk, int o0, int nP, const int2* __restrict__ parts, const int* __restrict__ qmap,
     typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab) {
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
-  constexpr int LL = L * L, LH = Sh::LH;
+  const int LL = ll;
+  constexpr int LH = Sh::LH;
   const int h = threadIdx.x & 1;
   const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
   const int pi = blockIdx.y;
   if (l >= LL) return;  // uniform over the pair; no barrier in this kernel
   const int o = pi / nP, p = pi - o * nP;
   const int q = qmap[((o0 + o) / nbands) * nk + parts[p].x];
-  C* base = tbuf + static_cast<size_t>(pi) * LL * L + static_cast<size_t>(h) * LL + l;
+  C* base = tbuf + static_cast<size_t>(pi) * LL * L;
+  const unsigned lo = (static_cast<unsigned>(h) * LL + l) * sizeof(C);
   C y[LH];
 #pragma unroll
-  for (int m = 0; m < LH; ++m) y[m] = base[static_cast<size_t>(2 * m) * LL];  // j1 = 2m + h
+  for (int m = 0; m < LH; ++m) y[m] = *lane_at(base + static_cast<size_t>(2 * m) * LL, lo);  // j1 = 2m + h
   split_fft_fwd<C, L>(y, h);  // y[k] at c1 = h L/2 + k
-  mul_table_line<C, T, LH>(y, vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l, LL);
+  mul_table_line_u<C, T, LH>(y, vtab + static_cast<size_t>(q) * LL * L,
+                             opaque((static_cast<unsigned>(h) * LH * LL + l) * sizeof(T)), LL);
   split_fft_inv<C, L>(y, h);
+  const unsigned so = opaque(lo);
 #pragma unroll
-  for (int m = 0; m < LH; ++m) base[static_cast<size_t>(2 * m) * LL] = y[m];
+  for (int m = 0; m < LH; ++m) *lane_at(base + static_cast<size_t>(2 * m) * LL, so) = y[m];
 }
 
 template <typename T, int L, typename TV = T>
 __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_energy_split(
-    const PairRef* __restrict__ pairs, const typename cx<T>::t* __restrict__ tbuf, const TV* __restrict__ vtab,
+    int ll, const PairRef* __restrict__ pairs, const typename cx<T>::t* __restrict__ tbuf, const TV* __restrict__ vtab,
     double* __restrict__ epart) {
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
-  constexpr int LL = L * L, LH = Sh::LH;
+  const int LL = ll;
+  constexpr int LH = Sh::LH;
   __shared__ double red[4];
   const int h = threadIdx.x & 1;
   const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);
@@ -505,28 +560,30 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_en
   double e = 0.0;
   if (l < LL) {
     const int q = pairs[pi].q;
-    const C* base = tbuf + static_cast<size_t>(pi) * LL * L + static_cast<size_t>(h) * LL + l;
+    const C* base = tbuf + static_cast<size_t>(pi) * LL * L;
+    const unsigned lo = (static_cast<unsigned>(h) * LL + l) * sizeof(C);
     C y[LH];
 #pragma unroll
-    for (int m = 0; m < LH; ++m) y[m] = base[static_cast<size_t>(2 * m) * LL];
+    for (int m = 0; m < LH; ++m) y[m] = *lane_at(base + static_cast<size_t>(2 * m) * LL, lo);
     split_fft_fwd<C, L>(y, h);
-    const TV* v = vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l;
+    const TV* v = vtab + static_cast<size_t>(q) * LL * L;
+    const unsigned lv = opaque((static_cast<unsigned>(h) * LH * LL + l) * sizeof(TV));
 #pragma unroll
     for (int k = 0; k < LH; ++k) {
       const double px = static_cast<double>(y[k].x), py = static_cast<double>(y[k].y);
-      e += static_cast<double>(v[static_cast<size_t>(k) * LL]) * (px * px + py * py);
+      e += static_cast<double>(*lane_at(v + static_cast<size_t>(k) * LL, lv)) * (px * px + py * py);
     }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
   __syncthreads();
-  if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * Sh::NLB + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 template <typename T, int L>
 __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC)) void k_acc_split(
-    int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
+    int n1, int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
     const double* __restrict__ gscale, double hscale, int backward) {
@@ -538,7 +595,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
   const int j1 = blockIdx.x * Sh::PL + pl;
-  const bool valid = j1 < L;
+  const bool valid = j1 < n1;
   const int o = blockIdx.y;
   T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
   // element (j1, 2m + h, col) of a grid: the lane's samples along axis 2
@@ -550,7 +607,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
     const int2 r = parts[p];
     C y[LH];
     if (valid) {
-      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * L + static_cast<size_t>(j1) * LL +
+      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * n1 + static_cast<size_t>(j1) * LL +
                      static_cast<size_t>(h) * LH * L + col;
 #pragma unroll
       for (int k = 0; k < LH; ++k) y[k] = src[k * L];  // row (j1, c2 = col), c3 = h L/2 + k
@@ -607,34 +664,37 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
 // FP64 one: forward axis 1 in FP32, kernel multiply and inverse in FP64
 // ---------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int nbands, int nk, int o0, int nP,
+__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nbands, int nk, int o0, int nP,
                                                                const int2* __restrict__ parts,
                                                                const int* __restrict__ qmap,
                                                                const float2* __restrict__ t32,
                                                                double2* __restrict__ t64,
                                                                const double* __restrict__ vtab) {
-  constexpr int LL = L * L, LH = L / 2, LPB = 128;
+  const int LL = ll;
+  constexpr int LH = L / 2, LPB = 128;
   const int h = threadIdx.x & 1;
   const int l = blockIdx.x * LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
   const int pi = blockIdx.y;
   if (l >= LL) return;  // uniform over the pair; no barrier in this kernel
   const int o = pi / nP, p = pi - o * nP;
   const int q = qmap[((o0 + o) / nbands) * nk + parts[p].x];
-  const size_t base = static_cast<size_t>(pi) * LL * L + static_cast<size_t>(h) * LL + l;
+  const size_t base = static_cast<size_t>(pi) * LL * L;
+  const unsigned le = static_cast<unsigned>(h) * LL + l;  // lane's element offset
   double2 y[LH];
   {
     float2 f[LH];
 #pragma unroll
-    for (int m = 0; m < LH; ++m) f[m] = t32[base + static_cast<size_t>(2 * m) * LL];  // j1 = 2m + h
+    for (int m = 0; m < LH; ++m) f[m] = *lane_at(t32 + base + static_cast<size_t>(2 * m) * LL, le * 8u);  // j1 = 2m + h
     split_fft_fwd<float2, L>(f, h);  // f[k] at c1 = h L/2 + k
 #pragma unroll
     for (int k = 0; k < LH; ++k) y[k] = cvt<double2>(f[k]);
   }
-  mul_table_line<double2, double, LH>(y, vtab + static_cast<size_t>(q) * LL * L + static_cast<size_t>(h) * LH * LL + l,
-                                      LL);
+  mul_table_line_u<double2, double, LH>(y, vtab + static_cast<size_t>(q) * LL * L,
+                                        opaque((static_cast<unsigned>(h) * LH * LL + l) * 8u), LL);
   split_fft_inv<double2, L>(y, h);
+  const unsigned so = opaque(le * 16u);
 #pragma unroll
-  for (int m = 0; m < LH; ++m) t64[base + static_cast<size_t>(2 * m) * LL] = y[m];
+  for (int m = 0; m < LH; ++m) *lane_at(t64 + base + static_cast<size_t>(2 * m) * LL, so) = y[m];
 }
 
 // ---------------------------------------------------------------------------
@@ -650,94 +710,91 @@ struct RegPolicy {
   static constexpr bool SPLIT_PLANE = !FP32 && L >= 40;
   static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 40;
   static constexpr bool SPLIT_ACC = FP32 ? L == 64 : L >= 40;
-  static constexpr int PLANE_NG = SPLIT_PLANE ? SplitShape<T, L>::NG : RegShape<T, L>::NG;
-  static constexpr int PLANE_NT = SPLIT_PLANE ? SplitShape<T, L>::NTP : RegShape<T, L>::NTP;
   static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
-  static constexpr int ACC_NG = SPLIT_ACC ? SplitShape<T, L>::NG : RegShape<T, L>::NG;
-  static constexpr int ACC_NT = SPLIT_ACC ? SplitShape<T, L>::NTP : RegShape<T, L>::NTP;
   static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
-  static constexpr int NLB = SPLIT_PENCIL ? SplitShape<T, L>::NLB : RegShape<T, L>::NLB;
   static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;
 };
 
 namespace {
 
-template <typename T, int L, bool EXPLICIT>
+// Grids N1 x L x L: the plane and accumulate passes are compiled for the
+// plane side L and take the plane count N1 at run time; the pencil pass is
+// compiled for the line length N1 and takes the line count L^2 at run time.
+// Each pass is dispatched on its own length.
+
+template <typename T, int L, bool EXPLICIT, typename TI = T>
 void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void* psi, const int2* parts,
                   const PairRef* pairs, typename cx<T>::t* tbuf) {
   using C = typename cx<T>::t;
+  using CI = typename cx<TI>::t;
   using Po = RegPolicy<T, L>;
+  const int n1 = in.grid[0];
   const long long bs = static_cast<long long>(in.band_stride);
   const int o0 = EXPLICIT ? 0 : b.o0, nP = EXPLICIT ? 1 : b.nP;
-  if constexpr (Po::SPLIT_PLANE) {
-    hipLaunchKernelGGL((k_plane_split<T, L, EXPLICIT>), dim3(Po::PLANE_NG, b.npairs), dim3(Po::PLANE_NT),
-                       Po::PLANE_LDS, p.stream, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
+  if constexpr (sizeof(TI) != sizeof(T)) {  // FOCK_MIXED: one-lane FP32 lines from FP64 orbitals
+    using Sh = RegShape<T, L>;
+    hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const CI*>(psi), o0, nP, parts, pairs, tbuf);
+  } else if constexpr (Po::SPLIT_PLANE) {
+    using Sh = SplitShape<T, L>;
+    hipLaunchKernelGGL((k_plane_split<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
   } else {
-    hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), dim3(Po::PLANE_NG, b.npairs), dim3(Po::PLANE_NT),
-                       Po::PLANE_LDS, p.stream, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
+    using Sh = RegShape<T, L>;
+    hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
   }
 }
 
 template <typename T, int L>
-hipError_t reg_apply_L(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                       const double* gscale, double hscale, bool backward) {
+void launch_pencil_apply(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
+                         typename cx<T>::t* tbuf, const T* vtab) {
+  const int ll = in.grid[1] * in.grid[2];
+  if constexpr (RegPolicy<T, L>::SPLIT_PENCIL) {
+    hipLaunchKernelGGL((k_pencil_apply_split<T, L>), dim3((ll + SplitShape<T, L>::LPB - 1) / SplitShape<T, L>::LPB,
+                       b.npairs), dim3(256), 0, p.stream, ll, in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+  } else {
+    hipLaunchKernelGGL((k_pencil_apply_reg<T, L>), dim3((ll + 255) / 256, b.npairs), dim3(256), 0, p.stream, ll,
+                       in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+  }
+}
+
+// returns the number of line blocks per pair (partial sums in epart)
+template <typename T, int L, typename TV = T>
+int launch_pencil_energy(const Plan& p, const Batch& b, const Instance& in, const PairRef* pairs,
+                         const typename cx<T>::t* tbuf, const TV* vtab, double* epart) {
+  const int ll = in.grid[1] * in.grid[2];
+  if constexpr (RegPolicy<T, L>::SPLIT_PENCIL) {
+    const int nlb = (ll + SplitShape<T, L>::LPB - 1) / SplitShape<T, L>::LPB;
+    hipLaunchKernelGGL((k_pencil_energy_split<T, L, TV>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, pairs,
+                       tbuf, vtab, epart);
+    return nlb;
+  } else {
+    const int nlb = (ll + 255) / 256;
+    hipLaunchKernelGGL((k_pencil_energy_reg<T, L, TV>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, pairs, tbuf,
+                       vtab, epart);
+    return nlb;
+  }
+}
+
+template <typename T, int L>
+void launch_acc(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
+                const void* psi, const double* occ, const double* kw, void* out, const double* gscale, double hscale,
+                bool backward) {
   using C = typename cx<T>::t;
-  using Po = RegPolicy<T, L>;
-  const Instance& in = p.inst[b.inst];
+  const int n1 = in.grid[0];
   const long long bs = static_cast<long long>(in.band_stride);
-  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
-  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
-  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
-  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
-  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
-  p.prof.begin(FOCK_K_PLANE, p.stream);
-  launch_plane<T, L, false>(p, b, in, psi, parts, nullptr, tbuf);
-  p.prof.end(FOCK_K_PLANE, p.stream);
-  p.prof.begin(FOCK_K_PENCIL, p.stream);
-  if constexpr (Po::SPLIT_PENCIL) {
-    hipLaunchKernelGGL((k_pencil_apply_split<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, in.nbands,
-                       in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+  if constexpr (RegPolicy<T, L>::SPLIT_ACC) {
+    using Sh = SplitShape<T, L>;
+    hipLaunchKernelGGL((k_acc_split<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.nO), dim3(Sh::NTP), Sh::LDS, p.stream,
+                       n1, in.nbands, bs, b.o0, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
+                       static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
   } else {
-    hipLaunchKernelGGL((k_pencil_apply_reg<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, in.nbands,
-                       in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+    using Sh = RegShape<T, L>;
+    hipLaunchKernelGGL((k_acc_reg<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.nO), dim3(Sh::NTP), Sh::LDS, p.stream,
+                       n1, in.nbands, bs, b.o0, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
+                       static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
   }
-  p.prof.end(FOCK_K_PENCIL, p.stream);
-  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
-  if constexpr (Po::SPLIT_ACC) {
-    hipLaunchKernelGGL((k_acc_split<T, L>), dim3(Po::ACC_NG, b.nO), dim3(Po::ACC_NT), Po::ACC_LDS, p.stream,
-                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ,
-                       kw, static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
-  } else {
-    hipLaunchKernelGGL((k_acc_reg<T, L>), dim3(Po::ACC_NG, b.nO), dim3(Po::ACC_NT), Po::ACC_LDS, p.stream,
-                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ,
-                       kw, static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
-  }
-  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
-  return hipGetLastError();
-}
-
-template <typename T, int L>
-hipError_t reg_energy_L(const Plan& p, const Batch& b, const void* psi, const double* occ) {
-  using C = typename cx<T>::t;
-  using Po = RegPolicy<T, L>;
-  const Instance& in = p.inst[b.inst];
-  const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
-  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
-  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
-  double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
-  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
-  launch_plane<T, L, true>(p, b, in, psi, nullptr, pairs, tbuf);
-  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
-  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
-  if constexpr (Po::SPLIT_PENCIL) {
-    hipLaunchKernelGGL((k_pencil_energy_split<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
-                       static_cast<const C*>(tbuf), vtab, epart);
-  } else {
-    hipLaunchKernelGGL((k_pencil_energy_reg<T, L>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
-                       static_cast<const C*>(tbuf), vtab, epart);
-  }
-  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
-  return launch_energy_reduce(p, b, occ, Po::NLB);
 }
 
 template <typename T, int L>
@@ -769,67 +826,11 @@ struct MixedPolicy {
 };
 
 template <int L>
-hipError_t mixed_apply_L(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                         const double* gscale, double hscale, bool backward) {
-  using Sh = RegShape<float, L>;
-  using Acc = RegPolicy<double, L>;
-  const Instance& in = p.inst[b.inst];
-  const long long bs = static_cast<long long>(in.band_stride);
-  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
-  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
-  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
-  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
-  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
-  double2* t64 = reinterpret_cast<double2*>(p.ws + p.tbuf64_off);
-  p.prof.begin(FOCK_K_PLANE, p.stream);
-  hipLaunchKernelGGL((k_plane_reg<float, L, false, double>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
-                     in.nbands, bs, static_cast<const double2*>(psi), b.o0, b.nP, parts,
-                     static_cast<const PairRef*>(nullptr), t32);
-  p.prof.end(FOCK_K_PLANE, p.stream);
-  p.prof.begin(FOCK_K_PENCIL, p.stream);
-  hipLaunchKernelGGL((k_pencil_apply_mixed<L>), dim3((L * L + 127) / 128, b.npairs), dim3(256), 0, p.stream, in.nbands,
-                     in.nk, b.o0, b.nP, parts, qmap, static_cast<const float2*>(t32), t64, vtab);
-  p.prof.end(FOCK_K_PENCIL, p.stream);
-  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
-  if constexpr (Acc::SPLIT_ACC) {
-    hipLaunchKernelGGL((k_acc_split<double, L>), dim3(Acc::ACC_NG, b.nO), dim3(Acc::ACC_NT), Acc::ACC_LDS, p.stream,
-                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const double2*>(t64),
-                       static_cast<const double2*>(psi), occ, kw, static_cast<double2*>(out), b.first, gscale, hscale,
-                       backward ? 1 : 0);
-  } else {
-    hipLaunchKernelGGL((k_acc_reg<double, L>), dim3(Acc::ACC_NG, b.nO), dim3(Acc::ACC_NT), Acc::ACC_LDS, p.stream,
-                       in.nbands, bs, b.o0, b.nP, parts, static_cast<const double2*>(t64),
-                       static_cast<const double2*>(psi), occ, kw, static_cast<double2*>(out), b.first, gscale, hscale,
-                       backward ? 1 : 0);
-  }
-  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
-  return hipGetLastError();
-}
-
-template <int L>
-hipError_t mixed_energy_L(const Plan& p, const Batch& b, const void* psi, const double* occ) {
-  using Sh = RegShape<float, L>;
-  using Po = RegPolicy<float, L>;
-  const Instance& in = p.inst[b.inst];
-  const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
-  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
-  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
-  double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
-  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
-  hipLaunchKernelGGL((k_plane_reg<float, L, true, double>), dim3(Sh::NG, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
-                     in.nbands, static_cast<long long>(in.band_stride), static_cast<const double2*>(psi), 0, 1,
-                     static_cast<const int2*>(nullptr), pairs, t32);
-  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
-  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
-  if constexpr (Po::SPLIT_PENCIL) {
-    hipLaunchKernelGGL((k_pencil_energy_split<float, L, double>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream,
-                       pairs, static_cast<const float2*>(t32), vtab, epart);
-  } else {
-    hipLaunchKernelGGL((k_pencil_energy_reg<float, L, double>), dim3(Po::NLB, b.npairs), dim3(256), 0, p.stream, pairs,
-                       static_cast<const float2*>(t32), vtab, epart);
-  }
-  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
-  return launch_energy_reduce(p, b, occ, Po::NLB);
+void launch_pencil_mixed(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
+                         const float2* t32, double2* t64, const double* vtab) {
+  const int ll = in.grid[1] * in.grid[2];
+  hipLaunchKernelGGL((k_pencil_apply_mixed<L>), dim3((ll + 127) / 128, b.npairs), dim3(256), 0, p.stream, ll,
+                     in.nbands, in.nk, b.o0, b.nP, parts, qmap, t32, t64, vtab);
 }
 
 template <int L>
@@ -845,58 +846,128 @@ void mixed_lds_attr(int lim) {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
 
-// the cubic lengths with register-line kernels
+// the axis lengths with register-line kernels
 #define FOCK_REG_L(X) X(24) X(32) X(40) X(48) X(64) X(72)
 
-hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                         const double* gscale, double hscale, bool backward) {
-#define CASE(N) \
-  case N: return mixed_apply_L<N>(p, b, psi, occ, out, gscale, hscale, backward);
-  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
-#undef CASE
-  return hipErrorInvalidValue;
-}
-
-hipError_t mixed_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
-#define CASE(N) \
-  case N: return mixed_energy_L<N>(p, b, psi, occ);
-  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
-#undef CASE
-  return hipErrorInvalidValue;
-}
+// `call` of the pass compiled for length n; false if there is none
+#define FOCK_REG_DISPATCH(n, call)                 \
+  [&]() -> bool {                                  \
+    switch (n) {                                   \
+      case 24: { constexpr int N = 24; call; return true; } \
+      case 32: { constexpr int N = 32; call; return true; } \
+      case 40: { constexpr int N = 40; call; return true; } \
+      case 48: { constexpr int N = 48; call; return true; } \
+      case 64: { constexpr int N = 64; call; return true; } \
+      case 72: { constexpr int N = 72; call; return true; } \
+      default: return false;                       \
+    }                                              \
+  }()
 
 template <typename T>
 hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                        const double* gscale, double hscale, bool backward) {
-#define CASE(N) \
-  case N: return reg_apply_L<T, N>(p, b, psi, occ, out, gscale, hscale, backward);
-  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
-#undef CASE
-  return hipErrorInvalidValue;
+  using C = typename cx<T>::t;
+  const Instance& in = p.inst[b.inst];
+  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
+  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
+  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
+  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
+  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
+  bool ok;
+  p.prof.begin(FOCK_K_PLANE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<T, N, false>(p, b, in, psi, parts, nullptr, tbuf)));
+  p.prof.end(FOCK_K_PLANE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_PENCIL, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[0], (launch_pencil_apply<T, N>(p, b, in, parts, qmap, tbuf, vtab)));
+  p.prof.end(FOCK_K_PENCIL, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale,
+                                                        backward)));
+  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
-#define CASE(N) \
-  case N: return reg_energy_L<T, N>(p, b, psi, occ);
-  switch (p.inst[b.inst].grid[0]) { FOCK_REG_L(CASE) default: break; }
-#undef CASE
-  return hipErrorInvalidValue;
+  using C = typename cx<T>::t;
+  const Instance& in = p.inst[b.inst];
+  const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
+  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
+  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
+  double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
+  bool ok;
+  int nlb = 0;
+  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<T, N, true>(p, b, in, psi, nullptr, pairs, tbuf)));
+  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_energy<T, N>(p, b, in, pairs, tbuf, vtab, epart)));
+  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  return launch_energy_reduce(p, b, occ, nlb);
 }
 
-template <typename T, int L>
-hipError_t reg_dft3_L(const Plan& p, int sign, int count, void* data, long long stride) {
-  using C = typename cx<T>::t;
-  using Sh = RegShape<T, L>;
-  C* d = static_cast<C*>(data);
-  if (sign < 0) {
-    hipLaunchKernelGGL((k_dft_plane_reg<T, L, -1>), dim3(Sh::NG, count), dim3(Sh::NTP), Sh::LDS, p.stream, d, stride);
-    hipLaunchKernelGGL((k_dft_pencil_reg<T, L, -1>), dim3(Sh::NLB, count), dim3(256), 0, p.stream, d, stride);
-  } else {
-    hipLaunchKernelGGL((k_dft_plane_reg<T, L, +1>), dim3(Sh::NG, count), dim3(Sh::NTP), Sh::LDS, p.stream, d, stride);
-    hipLaunchKernelGGL((k_dft_pencil_reg<T, L, +1>), dim3(Sh::NLB, count), dim3(256), 0, p.stream, d, stride);
-  }
+hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                         const double* gscale, double hscale, bool backward) {
+  const Instance& in = p.inst[b.inst];
+  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
+  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
+  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
+  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
+  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
+  double2* t64 = reinterpret_cast<double2*>(p.ws + p.tbuf64_off);
+  bool ok;
+  p.prof.begin(FOCK_K_PLANE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<float, N, false, double>(p, b, in, psi, parts, nullptr, t32)));
+  p.prof.end(FOCK_K_PLANE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_PENCIL, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[0], (launch_pencil_mixed<N>(p, b, in, parts, qmap, t32, t64, vtab)));
+  p.prof.end(FOCK_K_PENCIL, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc<double, N>(p, b, in, parts, t64, psi, occ, kw, out, gscale, hscale,
+                                                             backward)));
+  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t mixed_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+  const Instance& in = p.inst[b.inst];
+  const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
+  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
+  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
+  double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
+  bool ok;
+  int nlb = 0;
+  p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<float, N, true, double>(p, b, in, psi, nullptr, pairs, t32)));
+  p.prof.end(FOCK_K_ENERGY_PLANE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_ENERGY_PENCIL, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_energy<float, N, double>(p, b, in, pairs, t32, vtab,
+                                                                                      epart)));
+  p.prof.end(FOCK_K_ENERGY_PENCIL, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  return launch_energy_reduce(p, b, occ, nlb);
+}
+
+template <typename T, int L, int S>
+void dft_plane_L(const Plan& p, int n1, int count, typename cx<T>::t* d, long long stride) {
+  using Sh = RegShape<T, L>;
+  hipLaunchKernelGGL((k_dft_plane_reg<T, L, S>), dim3((n1 + Sh::PL - 1) / Sh::PL, count), dim3(Sh::NTP), Sh::LDS,
+                     p.stream, n1, d, stride);
+}
+
+template <typename T, int L, int S>
+void dft_pencil_L(const Plan& p, int ll, int count, typename cx<T>::t* d, long long stride) {
+  hipLaunchKernelGGL((k_dft_pencil_reg<T, L, S>), dim3((ll + 255) / 256, count), dim3(256), 0, p.stream, ll, d,
+                     stride);
 }
 
 template <typename T, int L>
@@ -911,15 +982,49 @@ void dft_reg_lds_attr(int lim) {
 #define FOCK_DFT_F32(X) X(16) X(24) X(32) X(40) X(48) X(64) X(72)
 #define FOCK_DFT_F64(X) X(16) X(24) X(32)
 
+bool reg_len(int n) { return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 72; }
+
+bool dft_len(fock_precision prec, int n) {
+  switch (n) {
+    case 16: case 24: case 32: return true;
+    case 40: case 48: case 64: case 72: return prec == FOCK_C64;
+    default: return false;
+  }
+}
+
+template <typename T, int S>
+hipError_t reg_dft3_t(const Plan& p, int inst, int count, void* data, long long stride) {
+  using C = typename cx<T>::t;
+  const int* g = p.inst[inst].grid;
+  C* d = static_cast<C*>(data);
+  bool ok = false;
+#define CASE(N) \
+  case N: dft_plane_L<T, N, S>(p, g[0], count, d, stride); ok = true; break;
+  if constexpr (sizeof(T) == 4) {
+    switch (g[1]) { FOCK_DFT_F32(CASE) default: break; }
+  } else {
+    switch (g[1]) { FOCK_DFT_F64(CASE) default: break; }
+  }
+#undef CASE
+  if (!ok) return hipErrorInvalidValue;
+  ok = false;
+#define CASE(N) \
+  case N: dft_pencil_L<T, N, S>(p, g[1] * g[2], count, d, stride); ok = true; break;
+  if constexpr (sizeof(T) == 4) {
+    switch (g[0]) { FOCK_DFT_F32(CASE) default: break; }
+  } else {
+    switch (g[0]) { FOCK_DFT_F64(CASE) default: break; }
+  }
+#undef CASE
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 }  // namespace
 
 bool reg_supported(fock_precision prec, const int grid[3]) {
   (void)prec;
-  if (grid[0] != grid[1] || grid[0] != grid[2]) return false;
-  switch (grid[0]) {
-    case 24: case 32: case 40: case 48: case 64: case 72: return true;
-    default: return false;
-  }
+  return grid[1] == grid[2] && reg_len(grid[0]) && reg_len(grid[1]);
 }
 
 size_t reg_lds_bytes(fock_precision prec, int L) {
@@ -944,27 +1049,15 @@ void prepare_reg_kernels(fock_precision prec, int lim) {
 }
 
 bool reg_dft_supported(fock_precision prec, const int grid[3]) {
-  if (grid[0] != grid[1] || grid[0] != grid[2]) return false;
-  switch (grid[0]) {
-    case 16: case 24: case 32: return true;
-    case 40: case 48: case 64: case 72: return prec == FOCK_C64;
-    default: return false;
-  }
+  return grid[1] == grid[2] && dft_len(prec, grid[0]) && dft_len(prec, grid[1]);
 }
 
 hipError_t launch_reg_dft3(const Plan& p, int inst, int sign, int count, void* data, long long stride) {
-  const int L = p.inst[inst].grid[0];
-#define CASE(N) \
-  case N: return reg_dft3_L<T, N>(p, sign, count, data, stride);
-  if (p.prec == FOCK_C64) {
-    using T = float;
-    switch (L) { FOCK_DFT_F32(CASE) default: break; }
-  } else {
-    using T = double;
-    switch (L) { FOCK_DFT_F64(CASE) default: break; }
-  }
-#undef CASE
-  return hipErrorInvalidValue;
+  if (p.prec == FOCK_C64)
+    return sign < 0 ? reg_dft3_t<float, -1>(p, inst, count, data, stride)
+                    : reg_dft3_t<float, +1>(p, inst, count, data, stride);
+  return sign < 0 ? reg_dft3_t<double, -1>(p, inst, count, data, stride)
+                  : reg_dft3_t<double, +1>(p, inst, count, data, stride);
 }
 
 void prepare_reg_dft_kernels(fock_precision prec, int lim) {

@@ -219,7 +219,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
     if (prec == FOCK_MIXED && !in.reg)
-      return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a cubic grid of 24, 32, 40, 48, 64 or 72 points");
+      return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 40, 48, 64, 72}");
   }
 
   // ---- batch shapes ----
@@ -394,7 +394,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   for (const auto& in : p->inst) {
     const size_t plane = static_cast<size_t>(in.grid[1]) * in.grid[2], tile = static_cast<size_t>(in.grid[0]) * in.grid[2];
     const size_t need = in.fused ? fused_lds_bytes(prec, in.grid[0]) + 256
-                        : in.reg ? reg_lds_bytes(prec, in.grid[0]) + 64
+                        : in.reg ? reg_lds_bytes(prec, in.grid[1]) + 64
                                  : std::max(plane, tile) * p->csize + 64;
     p->lds_needed = std::max(p->lds_needed, need);
   }
@@ -437,9 +437,10 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
         t.swap(r);
       } else if (in.reg) {
         // register-line three-pass path reads the table as [c1][c3][c2]
-        const int L = in.grid[0];
+        // (grids N1 x L x L)
+        const int n1 = in.grid[0], L = in.grid[1];
         std::vector<double> r(t.size());
-        for (int c1 = 0; c1 < L; ++c1)
+        for (int c1 = 0; c1 < n1; ++c1)
           for (int c2 = 0; c2 < L; ++c2)
             for (int c3 = 0; c3 < L; ++c3)
               r[(static_cast<size_t>(c1) * L + c3) * L + c2] = t[(static_cast<size_t>(c1) * L + c2) * L + c3];

@@ -11,7 +11,7 @@
 //                  class of G, inverse DFT (unnormalised, exp(+))
 //   to the sphere  forward DFT in place, gather sqrt(Omega)/N F(class of G)
 //
-// DFT passes: on cubic grids with register-line kernels (pass_reg.hip) a
+// DFT passes: on grids N1 x L x L with register-line kernels (pass_reg.hip) a
 // plane pass (axes 2 and 3, one line per lane) and a pencil pass (axis 1);
 // elsewhere per (grid, j1-plane) the axes 3 and 2 in LDS and per (grid,
 // c2-slab) the axis 1 in LDS (the LDS Stockham transforms of fft_lds.hpp),

@@ -83,6 +83,15 @@ CASES = [
     ((64, 64, 64), (1, 1, 1), 1, False, "c128"),
     ((72, 72, 72), (1, 1, 1), 1, True, "c128"),
     ((64, 64, 64), (2, 1, 1), 1, True, "c64"),
+    # register-line path on grids N1 x L x L: plane and accumulate passes of
+    # side L over N1 planes (a partial last plane group where N1 is not a
+    # multiple of the planes per workgroup), pencil pass of length N1
+    ((48, 64, 64), (1, 1, 1), 1, False, "c64"),
+    ((72, 48, 48), (1, 1, 1), 1, True, "c64"),
+    ((32, 24, 24), (2, 1, 1), 2, False, "c64"),
+    ((24, 32, 32), (2, 1, 1), 2, False, "c128"),
+    ((64, 40, 40), (1, 1, 1), 1, False, "c128"),
+    ((24, 72, 72), (1, 1, 1), 1, False, "c128"),
     # whole-pair path (cubic grids that fit one compute unit)
     ((32, 32, 32), (1, 1, 1), 3, False, "c64"),
     ((32, 32, 32), (2, 1, 1), 2, True, "c64"),
@@ -255,7 +264,8 @@ def test_whole_pair_explicit_k_pairs(kp, device):
 
 @pytest.mark.parametrize("grid,prec", [((32, 32, 32), "c128"), ((24, 24, 24), "c128"), ((48, 48, 48), "c64"),
                                        ((64, 64, 64), "c64"), ((72, 72, 72), "c64"), ((40, 40, 40), "c128"),
-                                       ((64, 64, 64), "c128")])
+                                       ((64, 64, 64), "c128"), ((48, 64, 64), "c64"), ((64, 40, 40), "c128"),
+                                       ((32, 24, 24), "c64")])
 def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
     """The register-line three-pass kernels and the LDS-Stockham three-pass
     kernels compute the same operator and energy (FP64: to rounding)."""
@@ -275,7 +285,8 @@ def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
 
 @pytest.mark.parametrize("grid,kmesh,nb", [((24, 24, 24), (2, 1, 1), 3), ((32, 32, 32), (1, 2, 1), 2),
                                            ((48, 48, 48), (1, 1, 1), 2), ((64, 64, 64), (1, 1, 1), 1),
-                                           ((72, 72, 72), (1, 1, 1), 1)])
+                                           ((72, 72, 72), (1, 1, 1), 1), ((32, 72, 72), (1, 1, 1), 1),
+                                           ((72, 24, 24), (2, 1, 1), 2)])
 def test_mixed_precision_matches_oracle(grid, kmesh, nb, device):
     """FP32 co-densities and forward transforms, FP64 multiply, inverse and
     accumulate: complex128 in and out, held to the FP32 tolerances."""
