@@ -302,29 +302,49 @@ def ragged(args):
         plan.close()
         del psi, out
         torch.cuda.empty_cache()
+    def one_at_a_time(prec):
+        """Sum over instances of one apply + energy on a plan of its own (after
+        one untimed call); also the energy FFT pairs of each instance."""
+        dt = np.complex64 if prec == "c64" else np.complex128
+        total, epairs = 0.0, []
+        for inst in insts:
+            p1 = fock.Plan([inst], precision=prec, device=device)
+            epairs.append(p1.stats()["energy_fft_pairs"])
+            ps = torch.from_numpy(inst.psi.astype(dt)).to(device)
+            oc = torch.from_numpy(inst.occ).to(device)
+            o = torch.empty_like(ps)
+            p1.fock_apply([ps], [oc], out=[o])
+            p1.fock_energy([ps], [oc])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            p1.fock_apply([ps], [oc], out=[o])
+            p1.fock_energy([ps], [oc])
+            torch.cuda.synchronize()
+            total += (time.perf_counter() - t0) * 1e3
+            p1.close()
+            del ps, o
+        return total, epairs
+
+    log("one-at-a-time FP32 plans")
+    ms32, epairs = one_at_a_time("c64")
     log("one-at-a-time FP64 plans")
-    ms64 = 0.0
-    for inst in insts:
-        p64 = fock.Plan([inst], precision="c128", device=device)
-        ps = torch.from_numpy(inst.psi).to(device)
-        oc = torch.from_numpy(inst.occ).to(device)
-        o = torch.empty_like(ps)
-        p64.fock_apply([ps], [oc], out=[o])
-        p64.fock_energy([ps], [oc])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p64.fock_apply([ps], [oc], out=[o])
-        p64.fock_energy([ps], [oc])
-        torch.cuda.synchronize()
-        ms64 += (time.perf_counter() - t0) * 1e3
-        p64.close()
-        del ps, o
+    ms64, _ = one_at_a_time("c128")
+    # algorithmic bytes of a step: 4 s N per ordered pair of the apply, 2 s N
+    # per FFT pair of the energy (swapped pairs folded)
+    alg = sum(8 * int(np.prod(i.grid)) * (4 * i.ordered_pairs() + 2 * e) for i, e in zip(insts, epairs))
+    gbs = alg / (ms / 1e3) / 1e9
     line = {"metric": "band-pair Fock applications/s, uneven batch (48 instances), FP32 one graph vs FP64 one-at-a-time",
             "value": round(pairs / (ms / 1e3), 1), "unit": "ordered band pairs/s (apply + energy per step)",
             "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64 (fp32 complex)",
             "data": "synthetic", "config": {"workload": "48 uneven instances", "ordered_pairs_per_step": pairs,
                                             "tuning": tuning},
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "kernel": "whole step (all instances, graph replay)",
+                         "algorithmic_bytes_per_step": alg},
+            "fp32_one_at_a_time": {"ms_per_step": round(ms32, 3), "pairs_per_s": round(pairs / (ms32 / 1e3), 1),
+                                   "batched_speedup": round(ms32 / ms, 3)},
             "fp64_one_at_a_time": {"ms_per_step": round(ms64, 3), "pairs_per_s": round(pairs / (ms64 / 1e3), 1)}}
     print(json.dumps(line), flush=True)
 
