@@ -330,10 +330,8 @@ hipError_t energy_batch_t(const Plan& p, const Batch& b, const void* psi, const 
   const C* tw = reinterpret_cast<const C*>(p.ws + p.tw_off);
   const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
   const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
-  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
   C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
   double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
-  double* ebsum = reinterpret_cast<double*>(p.ws + p.ebsum_off);
   const size_t lds_plane = static_cast<size_t>(g.n2) * g.n3 * sizeof(C);
   const size_t lds_tile = static_cast<size_t>(g.n1) * g.n3 * sizeof(C);
   p.prof.begin(FOCK_K_ENERGY_PLANE, p.stream);

@@ -270,7 +270,6 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_en
                                                            const typename cx<T>::t* __restrict__ tbuf,
                                                            const TV* __restrict__ vtab, double* __restrict__ epart) {
   using C = typename cx<T>::t;
-  using Sh = RegShape<T, L>;
   const int LL = ll;
   __shared__ double red[4];
   const int l = blockIdx.x * 256 + threadIdx.x;
