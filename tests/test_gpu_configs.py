@@ -33,7 +33,8 @@ def to_dev(a, device):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device)
 
 
-@pytest.mark.parametrize("grid,prec", [((12, 10, 9), "c128"), ((32, 32, 32), "c64"), ((16, 16, 16), "c128")])
+@pytest.mark.parametrize("grid,prec", [((12, 10, 9), "c128"), ((32, 32, 32), "c64"), ((16, 16, 16), "c128"),
+                                       ((32, 24, 24), "c128"), ((48, 64, 64), "c64")])
 def test_graph_replay_matches_eager(grid, prec, device):
     """Graph replays equal eager launches bitwise, with unrelated eager work
     and synchronisations between replays."""

@@ -319,7 +319,8 @@ def test_mixed_precision_backward(device):
 
 @pytest.mark.parametrize("grid,prec", [((16, 16, 16), "c64"), ((32, 32, 32), "c64"), ((16, 16, 16), "c128"),
                                        ((48, 48, 48), "c64"), ((32, 32, 32), "c128"), ((40, 40, 40), "c128"),
-                                       ((12, 10, 9), "c128"), ((24, 24, 24), "mixed")])
+                                       ((12, 10, 9), "c128"), ((24, 24, 24), "mixed"), ((48, 64, 64), "c64"),
+                                       ((24, 40, 40), "c128")])
 def test_padded_band_stride_gives_identical_results(grid, prec, device):
     """Bands stored band_stride = N + 37 elements apart (odd padding) give
     bitwise the same V_x u, overlap and E_x as the packed layout, and the
