@@ -34,7 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # copy-calibrated HBM traffic of the dominant FP32 kernel, written by
 # paper_1111_0716_amd.profile_summary from rocprofv3 counter runs of this script
-TRAFFIC_FILES = {"alpha": "profiles/{kind}_alpha_boron_32cubed_fp32_traffic.md"}
+TRAFFIC_FILES = {"alpha": "profiles/{kind}_alpha_boron_32cubed_fp32_traffic.md",
+                 "diff": "profiles/{kind}_diff_64cubed_fp32_traffic.md"}
 WORKLOADS = {
     "2": "alpha-boron-shaped rhombohedral cell a=9.56 bohr alpha=58.0 deg, 32^3 grid, 4x4x4 k-mesh "
          "(all 64 k' per k), 18 bands f=1, mu=0.106",
