@@ -123,3 +123,72 @@ def test_sweep_case_matches_oracle(i, device):
     assert ev <= tol["v"]
     assert ee <= tol["e"]
     assert em <= tol["v"]
+
+
+@pytest.mark.parametrize("i", range(16))
+def test_sweep_backward_matches_oracle_gradient(i, device):
+    """dE_x/du* from fock_energy_backward (co-densities recomputed) against
+    the oracle gradient, on the sweep's cases 64 + i."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    c = draw(NCASES + i)
+    log(f"backward case {i}: grid={c['grid']} kmesh={c['kmesh']} nb={c['nb']} prec={c['prec']} pad={c['pad']}")
+    lat = inputs.rhombohedral_lattice(c["edge"], c["angle"])
+    inst = inputs.small_instance(grid=c["grid"], kmesh=c["kmesh"], nbands=c["nb"], seed=(901, i), lattice=lat,
+                                 full_grid=c["full"])
+    dt = np.complex64 if c["prec"] == "c64" else np.complex128
+    psi_h = inst.psi.astype(dt)
+    n = inst.npoints
+    bs = n + c["pad"]
+    plan = fock.Plan([inst], precision=c["prec"], device=device, band_stride=[bs] if c["pad"] else None)
+    psi = torch.zeros((inst.nk, inst.nbands, bs), dtype=torch.complex64 if dt == np.complex64 else torch.complex128,
+                      device=device)
+    psi[:, :, :n] = torch.from_numpy(np.ascontiguousarray(psi_h)).to(device)
+    occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
+    o = Oracle.from_instance(inst)
+    gex = torch.full((1,), 0.75, dtype=torch.float64, device=device)
+    (g,) = plan.fock_energy_backward([psi], [occ], gex, 2.0 * o.dv)
+    torch.cuda.synchronize()
+    g = g[:, :, :n].cpu().numpy()
+    plan.close()
+    gref = 0.75 * o.gradient(psi_h.astype(np.complex128), inst.occ)
+    err = band_err(g, gref)
+    log(f"  grad err {err:.2e}")
+    assert err <= TOL[c["prec"]]["v"]
+
+
+@pytest.mark.parametrize("i", range(24))
+def test_sweep_dft3_matches_oracle(i, device):
+    """Batched 3-D DFT (both signs, unnormalised) on random grid shapes,
+    register-line N1 x L x L shapes included, against the oracle's DFT."""
+    import torch
+
+    from oracle import pw_oracle as pw
+    from paper_1111_0716_amd import fock
+
+    rng = np.random.default_rng([11110716, 902, i])
+    if i % 3 == 0:
+        l = int(rng.choice([16] + REG))
+        grid = (int(rng.choice([16] + REG)), l, l)
+    else:
+        grid = tuple(int(x) for x in rng.choice(SMOOTH + [48, 50, 54, 60, 64, 72], 3))
+    prec = "c64" if rng.random() < 0.5 else "c128"
+    n = int(np.prod(grid))
+    count = int(rng.integers(1, 4)) if n < 200_000 else 1
+    log(f"dft3 case {i}: grid={grid} prec={prec} count={count}")
+    inst = inputs.small_instance(grid=grid, kmesh=(1, 1, 1), nbands=1, seed=(902, i), full_grid=True)
+    plan = fock.Plan([inst], precision=prec, device=device)
+    x = rng.standard_normal((count, n)) + 1j * rng.standard_normal((count, n))
+    x = x.astype(np.complex64 if prec == "c64" else np.complex128)
+    tol = 1e-5 if prec == "c64" else 1e-12
+    for sign in (-1, +1):
+        d = torch.from_numpy(np.ascontiguousarray(x)).to(device)
+        plan.dft3(d, sign)
+        got = d.cpu().numpy()
+        for b in range(count):
+            ref = pw.dft3(x[b].astype(np.complex128), grid, sign)
+            err = np.linalg.norm(got[b] - ref) / np.linalg.norm(ref)
+            assert err <= tol, (sign, b, err)
+    plan.close()
