@@ -67,7 +67,7 @@ typedef enum {
  * orbitals and outputs; co-densities and forward transforms in FP32, kernel
  * multiply, inverse transforms and accumulate in FP64 (the paper's "some of
  * the FFTs in single precision"); grids N1 x L x L with N1 and L each 24,
- * 32, 40, 48, 64 or 72 only (FOCK_ERR_UNSUPPORTED otherwise). */
+ * 32, 36, 40, 48, 50, 54, 60, 64 or 72 only (FOCK_ERR_UNSUPPORTED otherwise). */
 typedef enum { FOCK_C128 = 0, FOCK_C64 = 1, FOCK_MIXED = 2 } fock_precision;
 
 /* One exchange problem ("instance").  All pointers are HOST pointers and are

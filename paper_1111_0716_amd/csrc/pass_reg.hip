@@ -1,7 +1,7 @@
 // Three-pass kernels with register-line FFTs for grids N1 x L x L that do not
-// take the whole-pair kernels, N1 and L in {24, 32, 40, 48, 64, 72}: a line
-// per lane (FP32 up to 48, FP64 up to 32) or a line per lane pair (longer
-// lines).  Same passes and batching as the LDS-Stockham kernels (paper,
+// take the whole-pair kernels, N1 and L in {24, 32, 36, 40, 48, 50, 54, 60,
+// 64, 72}: a line per lane (FP32 up to 60 in most passes, FP64 up to 32) or a
+// line per lane pair (longer lines).  Same passes and batching as the LDS-Stockham kernels (paper,
 // "Our Implementation": the band-pair loop on the GPU; NSIM-like blocks of
 // outputs x partners), but every 1-D transform runs in one thread's registers
 // on a whole line (reg_fft.hpp), a plane switches axes through one padded LDS
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_dft_penci
 }
 
 // ---------------------------------------------------------------------------
-// two-lane lines (L >= 64 FP32, L >= 40 FP64): each line lives in a lane pair
+// two-lane lines (L >= 64 FP32, L >= 36 FP64): each line lives in a lane pair
 // ---------------------------------------------------------------------------
 // The lanes 2i and 2i+1 share a line; lane h holds the samples 2m + h, or
 // after a forward transform the half h of the spectrum (split_fft_fwd /
@@ -706,9 +706,9 @@ __global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nband
 template <typename T, int L>
 struct RegPolicy {
   static constexpr bool FP32 = sizeof(T) == 4;
-  static constexpr bool SPLIT_PLANE = !FP32 && L >= 40;
-  static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 40;
-  static constexpr bool SPLIT_ACC = FP32 ? L == 64 : L >= 40;
+  static constexpr bool SPLIT_PLANE = !FP32 && L >= 36;
+  static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 36;
+  static constexpr bool SPLIT_ACC = FP32 ? L == 64 : L >= 36;
   static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;
@@ -846,7 +846,7 @@ void mixed_lds_attr(int lim) {
 }
 
 // the axis lengths with register-line kernels
-#define FOCK_REG_L(X) X(24) X(32) X(40) X(48) X(64) X(72)
+#define FOCK_REG_L(X) X(24) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72)
 
 // `call` of the pass compiled for length n; false if there is none
 #define FOCK_REG_DISPATCH(n, call)                 \
@@ -854,8 +854,12 @@ void mixed_lds_attr(int lim) {
     switch (n) {                                   \
       case 24: { constexpr int N = 24; call; return true; } \
       case 32: { constexpr int N = 32; call; return true; } \
+      case 36: { constexpr int N = 36; call; return true; } \
       case 40: { constexpr int N = 40; call; return true; } \
       case 48: { constexpr int N = 48; call; return true; } \
+      case 50: { constexpr int N = 50; call; return true; } \
+      case 54: { constexpr int N = 54; call; return true; } \
+      case 60: { constexpr int N = 60; call; return true; } \
       case 64: { constexpr int N = 64; call; return true; } \
       case 72: { constexpr int N = 72; call; return true; } \
       default: return false;                       \
@@ -978,15 +982,20 @@ void dft_reg_lds_attr(int lim) {
 }
 
 // the lengths with one-lane DFT kernels, per precision (longer FP64 lines would spill)
-#define FOCK_DFT_F32(X) X(16) X(24) X(32) X(40) X(48) X(64) X(72)
+#define FOCK_DFT_F32(X) X(16) X(24) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72)
 #define FOCK_DFT_F64(X) X(16) X(24) X(32)
 
-bool reg_len(int n) { return n == 24 || n == 32 || n == 40 || n == 48 || n == 64 || n == 72; }
+bool reg_len(int n) {
+  switch (n) {
+    case 24: case 32: case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: return true;
+    default: return false;
+  }
+}
 
 bool dft_len(fock_precision prec, int n) {
   switch (n) {
     case 16: case 24: case 32: return true;
-    case 40: case 48: case 64: case 72: return prec == FOCK_C64;
+    case 36: case 40: case 48: case 50: case 54: case 60: case 64: case 72: return prec == FOCK_C64;
     default: return false;
   }
 }

@@ -219,7 +219,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
     if (prec == FOCK_MIXED && !in.reg)
-      return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 40, 48, 64, 72}");
+      return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 36, 40, 48, 50, 54, 60, 64, 72}");
   }
 
   // ---- batch shapes ----

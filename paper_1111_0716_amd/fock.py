@@ -151,7 +151,7 @@ class Plan:
     ``precision``: "c64" (FP32 path), "c128" (FP64 path) or "mixed" (complex128
     orbitals and outputs, FP32 co-densities and forward transforms, FP64 kernel
     multiply, inverse transforms and accumulate; grids N1 x L x L, N1 and L in
-    24, 32, 40, 48, 64, 72)."""
+    24, 32, 36, 40, 48, 50, 54, 60, 64, 72)."""
 
     def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None, tuning=None,
                  band_stride=None):

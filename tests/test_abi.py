@@ -152,7 +152,8 @@ def test_mixed_precision_plans_need_register_line_grids():
     for grid, want in (((32, 32, 32), fock.FOCK_OK), ((72, 72, 72), fock.FOCK_OK), ((16, 16, 16), fock.FOCK_ERR_UNSUPPORTED),
                        ((12, 10, 9), fock.FOCK_ERR_UNSUPPORTED), ((48, 64, 64), fock.FOCK_OK),
                        ((24, 72, 72), fock.FOCK_OK), ((64, 48, 40), fock.FOCK_ERR_UNSUPPORTED),
-                       ((16, 32, 32), fock.FOCK_ERR_UNSUPPORTED)):
+                       ((16, 32, 32), fock.FOCK_ERR_UNSUPPORTED), ((60, 36, 36), fock.FOCK_OK),
+                       ((45, 45, 45), fock.FOCK_ERR_UNSUPPORTED)):
         d = fock.make_desc(inputs.cubic_lattice(10.0), grid, np.zeros((1, 3)), nbands=2, keep=keep)
         arr = (fock.FockDesc * 1)(d)
         h = ctypes.c_void_p()

@@ -92,6 +92,12 @@ CASES = [
     ((24, 32, 32), (2, 1, 1), 2, False, "c128"),
     ((64, 40, 40), (1, 1, 1), 1, False, "c128"),
     ((24, 72, 72), (1, 1, 1), 1, False, "c128"),
+    # lengths 36, 50, 54, 60 (one lane FP32; two lanes FP64)
+    ((60, 60, 60), (1, 1, 1), 1, False, "c64"),
+    ((36, 36, 36), (2, 1, 1), 2, True, "c128"),
+    ((50, 54, 54), (1, 1, 1), 1, False, "c64"),
+    ((36, 60, 60), (1, 1, 1), 1, False, "c128"),
+    ((54, 36, 36), (1, 2, 1), 2, False, "c64"),
     # whole-pair path (cubic grids that fit one compute unit)
     ((32, 32, 32), (1, 1, 1), 3, False, "c64"),
     ((32, 32, 32), (2, 1, 1), 2, True, "c64"),
@@ -265,7 +271,8 @@ def test_whole_pair_explicit_k_pairs(kp, device):
 @pytest.mark.parametrize("grid,prec", [((32, 32, 32), "c128"), ((24, 24, 24), "c128"), ((48, 48, 48), "c64"),
                                        ((64, 64, 64), "c64"), ((72, 72, 72), "c64"), ((40, 40, 40), "c128"),
                                        ((64, 64, 64), "c128"), ((48, 64, 64), "c64"), ((64, 40, 40), "c128"),
-                                       ((32, 24, 24), "c64")])
+                                       ((32, 24, 24), "c64"), ((60, 60, 60), "c64"), ((36, 36, 36), "c128"),
+                                       ((54, 50, 50), "c128")])
 def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
     """The register-line three-pass kernels and the LDS-Stockham three-pass
     kernels compute the same operator and energy (FP64: to rounding)."""
@@ -286,7 +293,8 @@ def test_register_line_path_matches_lds_path(grid, prec, device, monkeypatch):
 @pytest.mark.parametrize("grid,kmesh,nb", [((24, 24, 24), (2, 1, 1), 3), ((32, 32, 32), (1, 2, 1), 2),
                                            ((48, 48, 48), (1, 1, 1), 2), ((64, 64, 64), (1, 1, 1), 1),
                                            ((72, 72, 72), (1, 1, 1), 1), ((32, 72, 72), (1, 1, 1), 1),
-                                           ((72, 24, 24), (2, 1, 1), 2)])
+                                           ((72, 24, 24), (2, 1, 1), 2), ((60, 36, 36), (1, 1, 1), 2),
+                                           ((50, 50, 50), (1, 1, 1), 1)])
 def test_mixed_precision_matches_oracle(grid, kmesh, nb, device):
     """FP32 co-densities and forward transforms, FP64 multiply, inverse and
     accumulate: complex128 in and out, held to the FP32 tolerances."""

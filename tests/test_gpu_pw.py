@@ -50,7 +50,8 @@ def dev(a, device):
 @pytest.mark.parametrize("grid,prec", [((12, 10, 9), "c128"), ((16, 16, 16), "c64"), ((32, 32, 32), "c128"),
                                        ((5, 72, 6), "c64"), ((24, 20, 18), "c128"), ((72, 72, 72), "c64"),
                                        ((48, 64, 64), "c64"), ((72, 40, 40), "c64"), ((24, 16, 16), "c128"),
-                                       ((16, 32, 32), "c128")])
+                                       ((16, 32, 32), "c128"), ((60, 60, 60), "c64"), ((50, 54, 54), "c64"),
+                                       ((36, 36, 36), "c128")])
 def test_dft3_matches_oracle(grid, prec, device):
     from paper_1111_0716_amd import fock
 

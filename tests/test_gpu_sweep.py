@@ -19,7 +19,7 @@ from paper_1111_0716_amd import inputs
 pytestmark = pytest.mark.gpu
 
 SMOOTH = [5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32, 36, 40, 45]
-REG = [24, 32, 40, 48, 64, 72]
+REG = [24, 32, 36, 40, 48, 50, 54, 60, 64, 72]
 KMESHES = [(1, 1, 1), (2, 1, 1), (1, 2, 1), (1, 1, 2), (2, 2, 1)]
 TOL = {"c128": dict(e=1e-12, v=1e-12), "c64": dict(e=1e-6, v=1e-5), "mixed": dict(e=1e-6, v=1e-5)}
 # oracle budget per case: ordered pairs x N x (N1 + N2 + N3), the direct DFT's work
