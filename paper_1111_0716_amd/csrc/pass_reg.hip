@@ -702,13 +702,13 @@ __global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nband
 // Every variant reads and writes the pair buffer in the same layout, so each
 // pass picks its own: a line per lane where that fits the registers without
 // spilling, a line per lane pair otherwise, and by measurement where both fit
-// (FP32 64^3: two-lane pencil and accumulate; FP32 72^3: two-lane pencil).
+// (FP32 54-64: two-lane accumulate; FP32 64 and 72: two-lane pencil).
 template <typename T, int L>
 struct RegPolicy {
   static constexpr bool FP32 = sizeof(T) == 4;
   static constexpr bool SPLIT_PLANE = !FP32 && L >= 36;
   static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 36;
-  static constexpr bool SPLIT_ACC = FP32 ? L == 64 : L >= 36;
+  static constexpr bool SPLIT_ACC = FP32 ? (L >= 54 && L <= 64) : L >= 36;
   static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;
