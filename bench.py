@@ -5,11 +5,12 @@ Workload: the alpha-boron-shaped cell (rhombohedral a = 9.56 bohr, 58.0 deg),
 transfers), 18 bands, screened kernel mu = 0.106 bohr^-1; seeded random
 orthonormal orbitals (12 Ha cutoff).  1,327,104 ordered band pairs.
 
-A step is one pass of the whole path over that input: fock_apply with the
-band overlap M (co-density, FFTs, kernel multiply, accumulate, overlap),
-fock_energy (E_x) and fock_energy_backward (dE_x/dpsi*).  `value` counts
-ordered band pairs per step divided by the step time; the FP32 (complex64)
-path is the headline, the FP64 path is reported beside it.
+A step is one pass of the whole path over that input: fock_apply_energy
+(co-density, FFTs, kernel multiply, accumulate, the band overlap M, and E_x
+from the per-pair energies of the same transforms) and fock_energy_backward
+(dE_x/dpsi*, co-densities recomputed).  `value` counts ordered band pairs
+per step divided by the step time; the FP32 (complex64) path is the
+headline, the FP64 path is reported beside it.
 
 Per-kernel times come from HIP events the library records on its own
 stream around every launch, through the timed steps.  The roofline entry
@@ -166,11 +167,11 @@ def run_path(inst, prec, steps, warmup, device, profile=True):
     grad = torch.empty_like(psi)
     m = plan.meta[0]
     gex = torch.ones(1, dtype=torch.float64, device=device)
+    exbuf = torch.empty(1, dtype=torch.float64, device=device)
     scale = 2.0 * m["omega"] / m["npts"]
 
     def step():
-        plan.fock_apply([psi], [occ], out=[out], vmat=True)
-        ex = plan.fock_energy([psi], [occ])
+        _, _, ex = plan.fock_apply_energy([psi], [occ], out=[out], vmat=True, ex=exbuf)
         plan.fock_energy_backward([psi], [occ], gex, scale, out=[grad])
         return ex
 
@@ -287,8 +288,7 @@ def ragged(args):
         ex = torch.empty(len(insts), dtype=torch.float64, device=device)
 
         def step():
-            plan.fock_apply(psi, occ, out=out)
-            plan.fock_energy(psi, occ, ex=ex)
+            plan.fock_apply_energy(psi, occ, out=out, ex=ex)
 
         for _ in range(args.warmup):
             step()
@@ -314,12 +314,10 @@ def ragged(args):
             ps = torch.from_numpy(inst.psi.astype(dt)).to(device)
             oc = torch.from_numpy(inst.occ).to(device)
             o = torch.empty_like(ps)
-            p1.fock_apply([ps], [oc], out=[o])
-            p1.fock_energy([ps], [oc])
+            p1.fock_apply_energy([ps], [oc], out=[o])
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            p1.fock_apply([ps], [oc], out=[o])
-            p1.fock_energy([ps], [oc])
+            p1.fock_apply_energy([ps], [oc], out=[o])
             torch.cuda.synchronize()
             total += (time.perf_counter() - t0) * 1e3
             p1.close()
@@ -330,9 +328,15 @@ def ragged(args):
     ms32, epairs = one_at_a_time("c64")
     log("one-at-a-time FP64 plans")
     ms64, _ = one_at_a_time("c128")
-    # algorithmic bytes of a step: 4 s N per ordered pair of the apply, 2 s N
-    # per FFT pair of the energy (swapped pairs folded)
-    alg = sum(8 * int(np.prod(i.grid)) * (4 * i.ordered_pairs() + 2 * e) for i, e in zip(insts, epairs))
+    # algorithmic bytes of a step: 4 s N per ordered pair of the apply, and
+    # 2 s N per FFT pair of the energy (swapped pairs folded) where the energy
+    # needs transforms of its own, i.e. off the whole-pair path (cubic 16-32
+    # FP32 grids take their energy from the apply's transforms)
+    def whole_pair(g):
+        return g[0] == g[1] == g[2] and g[0] in (16, 24, 32)
+
+    alg = sum(8 * int(np.prod(i.grid)) * (4 * i.ordered_pairs() + (0 if whole_pair(i.grid) else 2 * e))
+              for i, e in zip(insts, epairs))
     gbs = alg / (ms / 1e3) / 1e9
     line = {"metric": "band-pair Fock applications/s, uneven batch (48 instances), FP32 one graph vs FP64 one-at-a-time",
             "value": round(pairs / (ms / 1e3), 1), "unit": "ordered band pairs/s (apply + energy per step)",

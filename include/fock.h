@@ -142,6 +142,19 @@ fock_status fock_apply(fock_plan_t plan, const void* const* psi, const double* c
  * a fixed order, so FP64 results are bitwise reproducible. */
 fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* const* occ, double* ex);
 
+/* fock_apply (V_x psi into vx_psi, the overlap into vmat if not NULL) and
+ * fock_energy (E_x into device FP64 ex[n_inst]) in one call.  Both are sums
+ * over the same band pairs of Eq. (2): on the whole-pair path the apply
+ * kernel also forms each pair's energy from the spectrum it has already
+ * transformed (FP64 partials per workgroup, summed in a fixed order), so no
+ * transform runs twice; other paths run their energy batches after the apply.
+ * vx_psi and vmat come out bitwise equal to fock_apply's.  E_x agrees with
+ * fock_energy's to rounding (FP64: bitwise reproducible from call to call,
+ * but summed over ordered pairs where fock_energy folds swapped ones).
+ * Errors as fock_apply, and FOCK_ERR_ARG if ex is NULL. */
+fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const double* const* occ,
+                              void* const* vx_psi, void* const* vmat, double* ex);
+
 /* Gradient of E_x: grad_psi[i] (psi layout, device) receives
  *   grad_ex[i] * scale * w_k * f_{k,n} * (V_x u)_{k,n}
  * with grad_ex a device FP64 array [n_inst] and scale a host number; the
@@ -229,8 +242,8 @@ typedef enum {
 fock_status fock_profile_enable(fock_plan_t plan, int enable);
 fock_status fock_profile_read(fock_plan_t plan, int kind, double* total_ms, int64_t* launches);
 
-/* Graph replay: when enabled, each of fock_apply, fock_energy and
- * fock_energy_backward records its whole launch sequence (every instance,
+/* Graph replay: when enabled, each of fock_apply, fock_apply_energy,
+ * fock_energy and fock_energy_backward records its whole launch sequence (every instance,
  * every batch) into one HIP graph on first use and replays it with a single
  * graph launch while the argument pointers stay the same (a new pointer set
  * records a new graph).  Needs a plan stream other than the legacy default

@@ -95,9 +95,11 @@ bool has_empty_k(const Instance& in) {
   return false;
 }
 
-// apply and backward share the batch loop; they differ in the output factor
+// apply and backward share the batch loop; they differ in the output factor.
+// with_energy: the whole-pair kernels also write their energy partials.
 fock_status run_apply(Plan* p, const void* const* psi, const double* const* occ, void* const* out,
-                      const double* gscale, double hscale, bool backward) {
+                      const double* gscale, double hscale, bool backward, bool with_energy = false) {
+  double* eblk = with_energy ? reinterpret_cast<double*>(p->ws + p->eblk_off) : nullptr;
   for (size_t i = 0; i < p->inst.size(); ++i) {
     if (has_empty_k(p->inst[i])) {
       const hipError_t e = launch_zero_outputs(*p, static_cast<int>(i), out[i]);
@@ -106,13 +108,49 @@ fock_status run_apply(Plan* p, const void* const* psi, const double* const* occ,
   }
   for (const FusedGroup& g : p->fused_groups) {
     const hipError_t e = launch_fused_apply(*p, g, psi[g.inst], occ[g.inst], out[g.inst],
-                                            gscale ? gscale + g.inst : nullptr, hscale, backward);
+                                            gscale ? gscale + g.inst : nullptr, hscale, backward,
+                                            eblk ? eblk + g.eblk0 : nullptr);
     if (e != hipSuccess) return hip_fail(e, "whole-pair apply launch");
   }
   for (const Batch& b : p->apply_batches) {
     const hipError_t e = launch_apply_batch(*p, b, psi[b.inst], occ[b.inst], out[b.inst],
                                             gscale ? gscale + b.inst : nullptr, hscale, backward);
     if (e != hipSuccess) return hip_fail(e, "apply batch launch");
+  }
+  return FOCK_OK;
+}
+
+// band overlaps M of every instance with a non-null vmat entry (vmat may be null)
+fock_status run_overlaps(Plan* p, const void* const* psi, void* const* vx_psi, void* const* vmat) {
+  if (!vmat) return FOCK_OK;
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    if (!vmat[i]) continue;
+    const hipError_t e = launch_overlap(*p, static_cast<int>(i), psi[i], vx_psi[i], vmat[i]);
+    if (e != hipSuccess) return hip_fail(e, "overlap launch");
+  }
+  return FOCK_OK;
+}
+
+// E_x of every instance into ex[i].  after_apply: the whole-pair instances
+// take their energy from the partials the apply just wrote; the others run
+// their energy batches.
+fock_status run_energy(Plan* p, const void* const* psi, const double* const* occ, double* ex, bool after_apply) {
+  for (const Batch& b : p->energy_batches) {
+    const bool fused = p->inst[b.inst].fused;
+    if (after_apply && fused) continue;
+    hipError_t e;
+    if (fused) {
+      e = launch_fused_energy(*p, b, psi[b.inst]);
+      if (e == hipSuccess) e = launch_energy_reduce(*p, b, occ[b.inst], 1);
+    } else {
+      e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
+    }
+    if (e != hipSuccess) return hip_fail(e, "energy batch launch");
+  }
+  for (size_t i = 0; i < p->inst.size(); ++i) {
+    const hipError_t e = after_apply && p->inst[i].fused ? launch_eblk_finish(*p, static_cast<int>(i), ex + i)
+                                                         : launch_energy_finish(*p, static_cast<int>(i), ex + i);
+    if (e != hipSuccess) return hip_fail(e, "energy finish launch");
   }
   return FOCK_OK;
 }
@@ -279,9 +317,7 @@ fock_status fock_set_stream(fock_plan_t plan, void* hip_stream) {
   p->stream = static_cast<hipStream_t>(hip_stream);
   if (p->use_graph && p->stream == nullptr) {
     p->use_graph = false;
-    p->g_apply.release();
-    p->g_energy.release();
-    p->g_backward.release();
+    p->release_graphs();
   }
   return FOCK_OK;
 }
@@ -300,14 +336,7 @@ fock_status fock_apply(fock_plan_t plan, const void* const* psi, const double* c
   auto enqueue = [&]() -> fock_status {
     fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false);
     if (st != FOCK_OK) return st;
-    if (vmat) {
-      for (size_t i = 0; i < p->inst.size(); ++i) {
-        if (!vmat[i]) continue;
-        const hipError_t e = launch_overlap(*p, static_cast<int>(i), psi[i], vx_psi[i], vmat[i]);
-        if (e != hipSuccess) return hip_fail(e, "overlap launch");
-      }
-    }
-    return FOCK_OK;
+    return run_overlaps(p, psi, vx_psi, vmat);
   };
   return with_graph(p, p->g_apply,
                     ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
@@ -324,25 +353,33 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
   if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
   if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
   if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
-  auto enqueue = [&]() -> fock_status {
-    for (const Batch& b : p->energy_batches) {
-      hipError_t e;
-      if (p->inst[b.inst].fused) {
-        e = launch_fused_energy(*p, b, psi[b.inst]);
-        if (e == hipSuccess) e = launch_energy_reduce(*p, b, occ[b.inst], 1);
-      } else {
-        e = launch_energy_batch(*p, b, psi[b.inst], occ[b.inst]);
-      }
-      if (e != hipSuccess) return hip_fail(e, "energy batch launch");
-    }
-    for (size_t i = 0; i < p->inst.size(); ++i) {
-      const hipError_t e = launch_energy_finish(*p, static_cast<int>(i), ex + i);
-      if (e != hipSuccess) return hip_fail(e, "energy finish launch");
-    }
-    return FOCK_OK;
-  };
   return with_graph(p, p->g_energy, ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ)},
                                             {reinterpret_cast<uintptr_t>(ex)}),
+                    [&]() { return run_energy(p, psi, occ, ex, false); });
+}
+
+fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const double* const* occ,
+                              void* const* vx_psi, void* const* vmat, double* ex) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  fock_status s = check_ready(p);
+  if (s != FOCK_OK) return s;
+  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
+  if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
+  auto enqueue = [&]() -> fock_status {
+    fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false, true);
+    if (st != FOCK_OK) return st;
+    if ((st = run_overlaps(p, psi, vx_psi, vmat)) != FOCK_OK) return st;
+    return run_energy(p, psi, occ, ex, true);
+  };
+  return with_graph(p, p->g_apply_energy,
+                    ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
+                                reinterpret_cast<const void* const*>(vmat)},
+                            {reinterpret_cast<uintptr_t>(vmat), reinterpret_cast<uintptr_t>(ex)}),
                     enqueue);
 }
 
@@ -376,9 +413,7 @@ fock_status fock_set_graph(fock_plan_t plan, int enable) {
     return set_error(FOCK_ERR_STATE, "graph replay needs a stream other than the legacy default stream");
   p->use_graph = enable != 0;
   if (!p->use_graph) {
-    p->g_apply.release();
-    p->g_energy.release();
-    p->g_backward.release();
+    p->release_graphs();
   }
   return FOCK_OK;
 }

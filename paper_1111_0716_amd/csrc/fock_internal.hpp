@@ -44,6 +44,7 @@ struct FusedGroup {
   size_t part_off = 0;
   int32_t npart = 0;
   int32_t nsplit = 1;  // partner slices per output (slices > 0 sum into partial buffers)
+  int32_t eblk0 = 0;   // first of its nout * nsplit energy partials (apply with energy)
 };
 
 struct Instance {
@@ -65,6 +66,7 @@ struct Instance {
   // workspace offsets (bytes)
   size_t vtab_off = 0, kw_off = 0, qmap_off = 0;
   int first_ebatch = 0, n_ebatches = 0;
+  int first_eblk = 0, n_eblk = 0;  // whole-pair apply-with-energy partials of this instance
 };
 
 // Event-based per-kernel timing (see fock_profile_enable).
@@ -108,6 +110,7 @@ struct Plan {
   size_t ebsum_off = 0, ebsum_bytes = 0;
   size_t partial_off = 0, partial_bytes = 0;
   size_t ovl_off = 0, ovl_bytes = 0;  // overlap split-K partials
+  size_t eblk_off = 0, eblk_bytes = 0;  // per-block energy partials of the whole-pair apply
   size_t total_bytes = 0;
   std::vector<unsigned char> host_image;  // constant prefix, uploaded by set_workspace
   unsigned char* ws = nullptr;            // device workspace (caller-owned)
@@ -119,12 +122,16 @@ struct Plan {
   size_t lds_needed = 0;   // largest dynamic LDS of any launch (+ static)
   mutable Profiler prof;
   bool use_graph = false;
-  GraphCache g_apply, g_energy, g_backward;
-  ~Plan() {
-    prof.release();
+  GraphCache g_apply, g_apply_energy, g_energy, g_backward;
+  void release_graphs() {
     g_apply.release();
+    g_apply_energy.release();
     g_energy.release();
     g_backward.release();
+  }
+  ~Plan() {
+    prof.release();
+    release_graphs();
   }
 };
 
@@ -138,6 +145,8 @@ hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, co
                               const double* gscale, double hscale, bool backward);
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 hipError_t launch_energy_finish(const Plan& p, int inst, double* ex);
+// E_x of a whole-pair instance from the per-block partials of an apply with energy
+hipError_t launch_eblk_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_zero_outputs(const Plan& p, int inst, void* out);
 hipError_t launch_zero_all_bands(const Plan& p, int inst, void* out);
 void prepare_dft_kernels(fock_precision prec, int lim);
@@ -162,8 +171,9 @@ void prepare_reg_kernels(fock_precision prec, int lim);
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                                   const double* gscale, double hscale, bool backward);
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
+// eblk: if not null, the apply also writes per-block energy partials there
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
-                              const double* gscale, double hscale, bool backward);
+                              const double* gscale, double hscale, bool backward, double* eblk);
 hipError_t launch_fused_energy(const Plan& p, const Batch& b, const void* psi);
 hipError_t launch_overlap(const Plan& p, int inst, const void* psi, const void* vx, void* vmat);
 

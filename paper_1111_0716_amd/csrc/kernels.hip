@@ -442,6 +442,16 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
   return hipGetLastError();
 }
 
+hipError_t launch_eblk_finish(const Plan& p, int inst, double* ex) {
+  const Instance& in = p.inst[inst];
+  const double factor = -0.5 * in.omega / static_cast<double>(in.npts);  // as in launch_energy_finish
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
+  hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(64), 0, p.stream,
+                     reinterpret_cast<const double*>(p.ws + p.eblk_off), in.first_eblk, in.n_eblk, factor, ex);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
+  return hipGetLastError();
+}
+
 hipError_t launch_energy_finish(const Plan& p, int inst, double* ex) {
   const Instance& in = p.inst[inst];
   // the tables hold v/N, so e = N * sum; E_x = -1/2 (Omega/N^2) * N * sum

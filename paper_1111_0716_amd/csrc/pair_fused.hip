@@ -303,8 +303,10 @@ __device__ __forceinline__ void load_codensity(typename cx<T>::t (*x)[L], const 
 }
 
 // x *= v for the thread's lines in layout C (table in C order), double-buffered.
-template <typename T, int L>
-__device__ __forceinline__ void mul_kernel(typename cx<T>::t (*x)[L], const T* __restrict__ v, uint32_t tv) {
+// EN: also es += v |x|^2 in FP64 (the pair's energy share of this thread).
+template <typename T, int L, bool EN = false>
+__device__ __forceinline__ void mul_kernel(typename cx<T>::t (*x)[L], const T* __restrict__ v, uint32_t tv,
+                                           double& es) {
   using Sh = FusedShape<T, L>;
   constexpr int E = Sh::LPT * L;
   constexpr int NB = E / kB;
@@ -324,6 +326,10 @@ __device__ __forceinline__ void mul_kernel(typename cx<T>::t (*x)[L], const T* _
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       const int e = b * kB + j;
+      if constexpr (EN) {
+        const double px = static_cast<double>(x[e / L][e % L].x), py = static_cast<double>(x[e / L][e % L].y);
+        es += static_cast<double>(vb[b & 1][j]) * (px * px + py * py);
+      }
       x[e / L][e % L] = cscale(x[e / L][e % L], vb[b & 1][j]);
     }
   }
@@ -332,13 +338,17 @@ __device__ __forceinline__ void mul_kernel(typename cx<T>::t (*x)[L], const T* _
 // ---------------------------------------------------------------------------
 // apply / backward: one workgroup per output band, all partners of its list
 // ---------------------------------------------------------------------------
-template <typename T, int L>
+// ENERGY (apply only): the forward transforms of the apply also give the
+// pair energies; each block writes w_k f_n sum_p w'_p f'_p sum_c v/N |P|^2
+// over its partners to eblk[block] (FP64), so that E_x needs no transforms
+// of its own.
+template <typename T, int L, bool ENERGY = false>
 __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     int nbands, long long bs, int o0, int nout, const typename cx<T>::t* __restrict__ psi,
     const int2* __restrict__ parts, int npart, int nsplit, int nk, const int* __restrict__ qmap,
     const T* __restrict__ vtab, const double* __restrict__ occ, const double* __restrict__ kw,
     typename cx<T>::t* __restrict__ out, typename cx<T>::t* __restrict__ partial, const double* __restrict__ gscale,
-    double hscale, int backward) {
+    double hscale, int backward, double* __restrict__ eblk) {
   using C = typename cx<T>::t;
   using Sh = FusedShape<T, L>;
   constexpr int LL = L * L;
@@ -369,6 +379,7 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
 #pragma unroll
       for (int i = 0; i < L; ++i) acc[l][i] = C{T(0), T(0)};
   }
+  double eacc = 0.0;  // ENERGY: sum over partners of w' f' (this thread's share of e)
   for (int p = p0; p < p1; ++p) {
     const int2 r = parts[p];
     const int pkm = r.x * nbands + r.y;
@@ -383,7 +394,16 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
       pf.tab = vtab + static_cast<size_t>(qmap[ok * nk + rn.x]) * npts;
     }
     fused_forward<T, L>(x, s, row0, col, pf);
-    mul_kernel<T, L>(x, vtab + static_cast<size_t>(qmap[ok * nk + r.x]) * npts, opaque_off(static_cast<uint32_t>(t)));
+    double esum = 0.0;
+    mul_kernel<T, L, ENERGY>(x, vtab + static_cast<size_t>(qmap[ok * nk + r.x]) * npts,
+                             opaque_off(static_cast<uint32_t>(t)), esum);
+    if constexpr (ENERGY) {
+      eacc += kw[r.x] * occ[pkm] * esum;
+      // keep the running sum a plain register across the partner loop (left
+      // to itself the compiler's schedule of it spills the lines: 924 bytes
+      // of scratch instead of 232)
+      asm volatile("" : "+v"(eacc));
+    }
     fused_inverse<T, L>(x, s, row0, col);
     const T coef = static_cast<T>(-kw[r.x] * occ[pkm] * f);
     const C* bm = psi + opaque_idx(om);
@@ -433,6 +453,19 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
       const uint32_t off = toff0 + static_cast<uint32_t>(l * Sh::RPT * LL);
 #pragma unroll
       for (int i = 0; i < L; ++i) bo[off + i * L] = acc[l][i];
+    }
+  }
+  if constexpr (ENERGY) {
+    __shared__ double ered[Sh::NT / 64];
+    double e = eacc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+    if ((t & 63) == 0) ered[t >> 6] = e;
+    __syncthreads();
+    if (t == 0) {
+      double tot = 0.0;
+      for (int w = 0; w < Sh::NT / 64; ++w) tot += ered[w];
+      eblk[blockIdx.x] = kw[ok] * occ[okn] * tot;
     }
   }
 }
@@ -527,21 +560,34 @@ __global__ __launch_bounds__(256) void k_add_partials(typename cx<T>::t* __restr
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename T, int L>
-hipError_t fused_apply_L(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
-                         const double* gscale, double hscale, bool backward) {
+template <typename T, int L, bool ENERGY>
+void launch_pair_fused(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
+                       const double* gscale, double hscale, bool backward, double* eblk) {
   using C = typename cx<T>::t;
   using Sh = FusedShape<T, L>;
   const Instance& in = p.inst[g.inst];
   const size_t lds = static_cast<size_t>(Sh::LDS) * sizeof(C);
-  p.prof.begin(FOCK_K_FUSED, p.stream);
   C* partial = reinterpret_cast<C*>(p.ws + p.partial_off);
-  hipLaunchKernelGGL((k_pair_fused<T, L>), dim3(g.nout * g.nsplit), dim3(Sh::NT), lds, p.stream, in.nbands,
+  hipLaunchKernelGGL((k_pair_fused<T, L, ENERGY>), dim3(g.nout * g.nsplit), dim3(Sh::NT), lds, p.stream, in.nbands,
                      static_cast<long long>(in.band_stride), g.o0, g.nout, static_cast<const C*>(psi),
                      reinterpret_cast<const int2*>(p.ws + g.part_off), g.npart, g.nsplit, in.nk,
                      reinterpret_cast<const int*>(p.ws + in.qmap_off), reinterpret_cast<const T*>(p.ws + in.vtab_off),
                      occ, reinterpret_cast<const double*>(p.ws + in.kw_off), static_cast<C*>(out), partial, gscale,
-                     hscale, backward ? 1 : 0);
+                     hscale, backward ? 1 : 0, eblk);
+}
+
+// eblk: per-block energy partials of this group (null: no energy)
+template <typename T, int L>
+hipError_t fused_apply_L(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
+                         const double* gscale, double hscale, bool backward, double* eblk) {
+  using C = typename cx<T>::t;
+  const Instance& in = p.inst[g.inst];
+  C* partial = reinterpret_cast<C*>(p.ws + p.partial_off);
+  p.prof.begin(FOCK_K_FUSED, p.stream);
+  if (eblk)
+    launch_pair_fused<T, L, true>(p, g, psi, occ, out, gscale, hscale, backward, eblk);
+  else
+    launch_pair_fused<T, L, false>(p, g, psi, occ, out, gscale, hscale, backward, nullptr);
   p.prof.end(FOCK_K_FUSED, p.stream);
   if (g.nsplit > 1) {
     const size_t npts = static_cast<size_t>(in.npts);
@@ -574,14 +620,14 @@ hipError_t fused_energy_L(const Plan& p, const Batch& b, const void* psi) {
 
 template <typename T>
 hipError_t fused_apply_t(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
-                         const double* gscale, double hscale, bool backward) {
+                         const double* gscale, double hscale, bool backward, double* eblk) {
   switch (p.inst[g.inst].grid[0]) {
-    case 16: return fused_apply_L<T, 16>(p, g, psi, occ, out, gscale, hscale, backward);
+    case 16: return fused_apply_L<T, 16>(p, g, psi, occ, out, gscale, hscale, backward, eblk);
     case 24:
-      if constexpr (sizeof(T) == 4) return fused_apply_L<T, 24>(p, g, psi, occ, out, gscale, hscale, backward);
+      if constexpr (sizeof(T) == 4) return fused_apply_L<T, 24>(p, g, psi, occ, out, gscale, hscale, backward, eblk);
       break;
     case 32:
-      if constexpr (sizeof(T) == 4) return fused_apply_L<T, 32>(p, g, psi, occ, out, gscale, hscale, backward);
+      if constexpr (sizeof(T) == 4) return fused_apply_L<T, 32>(p, g, psi, occ, out, gscale, hscale, backward, eblk);
       break;
     default: break;
   }
@@ -605,7 +651,8 @@ hipError_t fused_energy_t(const Plan& p, const Batch& b, const void* psi) {
 
 template <typename T, int L>
 void fused_lds_attr(int lim) {
-  const void* fs[] = {reinterpret_cast<const void*>(&k_pair_fused<T, L>),
+  const void* fs[] = {reinterpret_cast<const void*>(&k_pair_fused<T, L, false>),
+                      reinterpret_cast<const void*>(&k_pair_fused<T, L, true>),
                       reinterpret_cast<const void*>(&k_pair_energy_fused<T, L>)};
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
@@ -645,9 +692,9 @@ void prepare_fused_kernels(fock_precision prec, int lim) {
 }
 
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
-                              const double* gscale, double hscale, bool backward) {
-  return p.prec == FOCK_C128 ? fused_apply_t<double>(p, g, psi, occ, out, gscale, hscale, backward)
-                             : fused_apply_t<float>(p, g, psi, occ, out, gscale, hscale, backward);
+                              const double* gscale, double hscale, bool backward, double* eblk) {
+  return p.prec == FOCK_C128 ? fused_apply_t<double>(p, g, psi, occ, out, gscale, hscale, backward, eblk)
+                             : fused_apply_t<float>(p, g, psi, occ, out, gscale, hscale, backward, eblk);
 }
 
 hipError_t launch_fused_energy(const Plan& p, const Batch& b, const void* psi) {

@@ -387,6 +387,20 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->ovl_off = off;
   for (const auto& in : p->inst) p->ovl_bytes = std::max(p->ovl_bytes, overlap_scratch_bytes(in));
   off = align_up(off + p->ovl_bytes);
+  // energy partials of the whole-pair apply: one per block, contiguous per instance
+  int neblk = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    p->inst[i].first_eblk = neblk;
+    for (FusedGroup& g : p->fused_groups) {
+      if (g.inst != i) continue;
+      g.eblk0 = neblk;
+      neblk += g.nout * g.nsplit;
+    }
+    p->inst[i].n_eblk = neblk - p->inst[i].first_eblk;
+  }
+  p->eblk_off = off;
+  p->eblk_bytes = static_cast<size_t>(std::max(neblk, 1)) * sizeof(double);
+  off = align_up(off + p->eblk_bytes);
   p->ebsum_off = off;
   p->ebsum_bytes = static_cast<size_t>(std::max(slot, 1)) * sizeof(double);
   off = align_up(off + p->ebsum_bytes);

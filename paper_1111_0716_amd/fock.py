@@ -22,7 +22,7 @@ FOCK_C128, FOCK_C64, FOCK_MIXED = 0, 1, 2
 PRECISIONS = {"c128": FOCK_C128, "c64": FOCK_C64, "mixed": FOCK_MIXED}
 
 EXPORTED = ["fock_plan", "fock_plan_tuned", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
-            "fock_energy", "fock_energy_backward", "fock_pw_to_grid", "fock_grid_to_pw", "fock_apply_pw", "fock_dft3",
+            "fock_apply_energy", "fock_energy", "fock_energy_backward", "fock_pw_to_grid", "fock_grid_to_pw", "fock_apply_pw", "fock_dft3",
             "fock_plan_stats", "fock_profile_enable", "fock_profile_read", "fock_set_graph", "fock_destroy",
             "fock_status_string", "fock_last_error"]
 KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
@@ -72,6 +72,8 @@ def lib():
         L.fock_set_stream.argtypes = [c_void_p, c_void_p]
         L.fock_apply.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p)]
         L.fock_energy.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]
+        L.fock_apply_energy.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                        POINTER(c_void_p), c_void_p]
         L.fock_energy_backward.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_double,
                                            POINTER(c_void_p)]
         L.fock_pw_to_grid.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -232,6 +234,26 @@ class Plan:
                                _ptrs([x.data_ptr() for x in out]),
                                _ptrs([x.data_ptr() for x in mats]) if mats else None))
         return out, mats
+
+    def fock_apply_energy(self, psi, occ, out=None, vmat=False, ex=None):
+        """fock_apply and fock_energy in one call; returns (outputs, overlaps
+        or None, E_x as a float64 tensor [n_inst])."""
+        psi, occ = _aslist(psi), _aslist(occ)
+        for i, (p, o) in enumerate(zip(psi, occ)):
+            self._check_psi(p, i)
+            self._check_occ(o, i)
+        out = [self.torch.empty_like(p) for p in psi] if out is None else _aslist(out)
+        mats = None
+        if vmat:
+            mats = [self.torch.empty((m["nk"], m["nbands"], m["nbands"]), dtype=self.cdtype, device=self.device)
+                    for m in self.meta]
+        if ex is None:
+            ex = self.torch.empty(len(psi), dtype=self.torch.float64, device=self.device)
+        self._sync_stream()
+        check(lib().fock_apply_energy(self.handle, _ptrs([p.data_ptr() for p in psi]),
+                                      _ptrs([o.data_ptr() for o in occ]), _ptrs([x.data_ptr() for x in out]),
+                                      _ptrs([x.data_ptr() for x in mats]) if mats else None, c_void_p(ex.data_ptr())))
+        return out, mats, ex
 
     def fock_energy(self, psi, occ, ex=None):
         psi, occ = _aslist(psi), _aslist(occ)

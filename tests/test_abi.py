@@ -103,6 +103,7 @@ def test_calls_before_workspace_are_state_errors():
     one = fock._ptrs([1])
     assert L.fock_apply(h, one, one, one, None) == fock.FOCK_ERR_STATE
     assert L.fock_energy(h, one, one, ctypes.c_void_p(1)) == fock.FOCK_ERR_STATE
+    assert L.fock_apply_energy(h, one, one, fock._ptrs([2]), None, ctypes.c_void_p(1)) == fock.FOCK_ERR_STATE
     assert L.fock_energy_backward(h, one, one, ctypes.c_void_p(1), 1.0, one) == fock.FOCK_ERR_STATE
     npw_max = (ctypes.c_int32 * 1)(4)
     assert L.fock_pw_to_grid(h, one, one, one, npw_max, one) == fock.FOCK_ERR_STATE

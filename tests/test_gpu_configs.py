@@ -54,21 +54,30 @@ def test_graph_replay_matches_eager(grid, prec, device):
         ex_e = plan.fock_energy([psi], [occ]).clone()
         g = torch.ones(1, dtype=torch.float64, device=device)
         (gr_e,) = plan.fock_energy_backward([psi], [occ], g, 0.5)
+        _, _, exa_e = plan.fock_apply_energy([psi], [occ])
+        exa_e = exa_e.clone()
         plan.set_graph(True)
         out_g = torch.empty_like(psi)
+        out_a = torch.empty_like(psi)
         gr_g = torch.empty_like(psi)
         ex_buf = torch.empty(1, dtype=torch.float64, device=device)
+        exa_buf = torch.empty(1, dtype=torch.float64, device=device)
         for rep in range(3):
             out_g.zero_()
+            out_a.zero_()
             gr_g.zero_()
+            exa_buf.zero_()
             junk = torch.randn(1000, device=device).sum()  # unrelated eager work
             plan.fock_apply([psi], [occ], out=[out_g])
             plan.fock_energy([psi], [occ], ex=ex_buf)
             plan.fock_energy_backward([psi], [occ], g, 0.5, out=[gr_g])
+            plan.fock_apply_energy([psi], [occ], out=[out_a], ex=exa_buf)
             stream.synchronize()
             assert torch.equal(out_g, out_e), f"replay {rep}"
+            assert torch.equal(out_a, out_e), f"replay {rep}"
             assert torch.equal(gr_g, gr_e), f"replay {rep}"
             assert ex_buf.item() == ex_e.item()
+            assert exa_buf.item() == exa_e.item()
             del junk
         plan.close()
 

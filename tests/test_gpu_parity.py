@@ -369,3 +369,69 @@ def test_zero_occupations_give_zero_exchange(grid, prec, device):
         inst = inst.astype(np.complex64)
     g = run_gpu(inst, prec, device, vmat=True)
     assert np.all(g["vx"] == 0) and g["ex"] == 0.0 and np.all(g["vmat"] == 0)
+
+
+@pytest.mark.parametrize("grid,kmesh,nb,prec", [((32, 32, 32), (2, 1, 1), 3, "c64"), ((24, 24, 24), (1, 2, 1), 3, "c64"),
+                                                ((16, 16, 16), (2, 1, 1), 3, "c128"), ((16, 16, 16), (1, 1, 1), 4, "c64"),
+                                                ((24, 24, 24), (2, 1, 1), 2, "c128"), ((12, 10, 9), (2, 1, 1), 3, "c128"),
+                                                ((48, 40, 40), (1, 1, 1), 2, "mixed")])
+def test_apply_energy_matches_apply_and_energy(grid, kmesh, nb, prec, device):
+    """fock_apply_energy: V_x u and the overlap bitwise equal to fock_apply's,
+    E_x equal to fock_energy's to rounding (bitwise where the path has no
+    whole-pair kernels) and to the oracle within the path's tolerance."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    log(f"apply+energy grid={grid} kmesh={kmesh} nb={nb} prec={prec}")
+    inst = inputs.small_instance(grid=grid, kmesh=kmesh, nbands=nb, seed=(213, grid[0]), full_grid=grid[0] == 16)
+    dt = np.complex64 if prec == "c64" else np.complex128
+    psi = torch.from_numpy(np.ascontiguousarray(inst.psi.astype(dt))).to(device)
+    occ = torch.from_numpy(inst.occ).to(device)
+    plan = fock.Plan([inst], precision=prec, device=device)
+    (v0,), (m0,) = plan.fock_apply([psi], [occ], vmat=True)
+    e0 = plan.fock_energy([psi], [occ]).item()
+    (v1,), (m1,), ex = plan.fock_apply_energy([psi], [occ], vmat=True)
+    e1 = ex.item()
+    (v2,), (m2,), ex2 = plan.fock_apply_energy([psi], [occ], vmat=True)
+    torch.cuda.synchronize()
+    assert torch.equal(v1, v0) and torch.equal(m1, m0)
+    assert torch.equal(v2, v1) and torch.equal(m2, m1) and ex2.item() == e1
+    fused = grid[0] == grid[1] == grid[2] and (grid[0] in (16, 24, 32) if prec == "c64" else grid[0] == 16)
+    if fused:
+        assert abs(e1 - e0) <= (1e-13 if prec == "c128" else 1e-7) * abs(e0)
+    else:
+        assert e1 == e0
+    o = Oracle.from_instance(inst)
+    _, eref = o.apply(inst.psi.astype(dt).astype(np.complex128), inst.occ)
+    tol = TOL["c128"]["e"] if prec == "c128" else TOL["c64"]["e"]
+    log(f"  E_x {e1:.12e} (energy call {e0:.12e}, oracle {eref:.12e})")
+    assert abs(e1 - eref) <= tol * abs(eref)
+    plan.close()
+
+
+def test_apply_energy_mixed_plan_and_empty_partner_lists(device):
+    """One plan with a whole-pair instance (explicit k pairs, one k without
+    partners) and a register-line instance: E_x of each against the oracle."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    a = inputs.small_instance(grid=(32, 32, 32), kmesh=(2, 2, 1), nbands=2, seed=(214, 0))
+    b = inputs.small_instance(grid=(40, 40, 40), kmesh=(2, 1, 1), nbands=2, seed=(214, 1))
+    kp = np.array([[0, 0], [0, 1], [1, 3], [2, 2], [2, 0]], dtype=np.int32)  # k = 3 has no partner
+    insts = [a.astype(np.complex64), b.astype(np.complex64)]
+    plan = fock.Plan(insts, precision="c64", device=device, kpairs=[kp, None])
+    psi = [torch.from_numpy(np.ascontiguousarray(i.psi)).to(device) for i in insts]
+    occ = [torch.from_numpy(i.occ).to(device) for i in insts]
+    vx, _, ex = plan.fock_apply_energy(psi, occ)
+    e0 = plan.fock_energy(psi, occ)
+    torch.cuda.synchronize()
+    for i, (inst, k) in enumerate(zip(insts, [kp, None])):
+        o = Oracle.from_instance(inst, kpairs=k)
+        vref, eref = o.apply(inst.psi.astype(np.complex128), inst.occ)
+        assert band_err(vx[i].cpu().numpy(), vref) <= TOL["c64"]["v"]
+        assert abs(ex[i].item() - eref) <= TOL["c64"]["e"] * abs(eref)
+        assert abs(ex[i].item() - e0[i].item()) <= 1e-7 * abs(eref)
+    assert np.all(vx[0].cpu().numpy()[3] == 0)
+    plan.close()
