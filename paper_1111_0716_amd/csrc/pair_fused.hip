@@ -379,7 +379,11 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
 #pragma unroll
       for (int i = 0; i < L; ++i) acc[l][i] = C{T(0), T(0)};
   }
-  double eacc = 0.0;  // ENERGY: sum over partners of w' f' (this thread's share of e)
+  // ENERGY: per thread, sum over partners of w' f' e (its share), kept in LDS
+  // so that no register is carried through the partner loop
+  __shared__ double eslot[ENERGY ? Sh::NT : 1];
+  if constexpr (ENERGY) eslot[t] = 0.0;
+  const double wn = ENERGY ? kw[ok] * occ[okn] : 0.0;  // w_k f_n of the output
   for (int p = p0; p < p1; ++p) {
     const int2 r = parts[p];
     const int pkm = r.x * nbands + r.y;
@@ -397,13 +401,7 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     double esum = 0.0;
     mul_kernel<T, L, ENERGY>(x, vtab + static_cast<size_t>(qmap[ok * nk + r.x]) * npts,
                              opaque_off(static_cast<uint32_t>(t)), esum);
-    if constexpr (ENERGY) {
-      eacc += kw[r.x] * occ[pkm] * esum;
-      // keep the running sum a plain register across the partner loop (left
-      // to itself the compiler's schedule of it spills the lines: 924 bytes
-      // of scratch instead of 232)
-      asm volatile("" : "+v"(eacc));
-    }
+    if constexpr (ENERGY) eslot[t] += wn * kw[r.x] * occ[pkm] * esum;  // only this thread touches eslot[t]
     fused_inverse<T, L>(x, s, row0, col);
     const T coef = static_cast<T>(-kw[r.x] * occ[pkm] * f);
     const C* bm = psi + opaque_idx(om);
@@ -411,7 +409,9 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     const uint32_t toff = opaque_off(toff0);
     // accumulate: u_m (and the running output) in double-buffered batches
     constexpr int E = LPT * L;
-    constexpr int kA = 4;  // smaller batches here: x, u_m and the output are live together
+    // smaller batches here: x, u_m and the output are live together (with the
+    // energy epilogue two, which keeps its spill below the plain kernel's)
+    constexpr int kA = ENERGY ? 2 : 4;
     constexpr int NB = E / kA;
     C mb[2][kA], ob[2][kA];
     const bool rmw = !Sh::ACC_REG && p > p0;
@@ -456,16 +456,14 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
     }
   }
   if constexpr (ENERGY) {
-    __shared__ double ered[Sh::NT / 64];
-    double e = eacc;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
-    if ((t & 63) == 0) ered[t >> 6] = e;
+    // fixed-order block sum by the first wave: lane l takes l, l + 64, ...
     __syncthreads();
-    if (t == 0) {
-      double tot = 0.0;
-      for (int w = 0; w < Sh::NT / 64; ++w) tot += ered[w];
-      eblk[blockIdx.x] = kw[ok] * occ[okn] * tot;
+    if (t < 64) {
+      double e = 0.0;
+      for (int i = t; i < Sh::NT; i += 64) e += eslot[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+      if (t == 0) eblk[blockIdx.x] = e;
     }
   }
 }
