@@ -34,6 +34,7 @@ struct Batch {
   int32_t npairs = 0;   // pairs in the batch (apply: nO*nP)
   int32_t slot = 0;
   int32_t per_wg = 1;   // energy on the whole-pair path: pairs per workgroup
+  int32_t eslot = -1;   // apply batch of the register-line path: its energy sum slot
 };
 
 // Outputs o0..o0+nout-1 of one instance on the whole-pair path, all sharing
@@ -67,6 +68,7 @@ struct Instance {
   size_t vtab_off = 0, kw_off = 0, qmap_off = 0;
   int first_ebatch = 0, n_ebatches = 0;
   int first_eblk = 0, n_eblk = 0;  // whole-pair apply-with-energy partials of this instance
+  int first_aslot = 0, n_aslot = 0;  // register-line apply-with-energy sum slots
 };
 
 // Event-based per-kernel timing (see fock_profile_enable).
@@ -141,7 +143,7 @@ void clear_error();
 
 // kernel launchers (kernels.hip); return hipSuccess or the launch error
 hipError_t prepare_kernels(fock_precision prec, size_t* max_lds);
-hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* vx,
+hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* vx, bool energy,
                               const double* gscale, double hscale, bool backward);
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 hipError_t launch_energy_finish(const Plan& p, int inst, double* ex);
@@ -168,8 +170,15 @@ void prepare_fused_kernels(fock_precision prec, int lim);
 bool reg_supported(fock_precision prec, const int grid[3]);
 size_t reg_lds_bytes(fock_precision prec, int L);
 void prepare_reg_kernels(fock_precision prec, int lim);
+// energy: the pencil pass also writes the batch's weighted pair energies to
+// its slot (b.eslot); only where reg_apply_energy(inst)
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                                  const double* gscale, double hscale, bool backward);
+                                  const double* gscale, double hscale, bool backward, bool energy);
+bool reg_apply_energy(const Plan& p, int inst);
+// ebsum[slot] = fixed-order sum of the first n energy partials (epart)
+hipError_t launch_sum_slot(const Plan& p, long long n, int slot);
+// E_x of a register-line instance from its apply-with-energy slots
+hipError_t launch_aslot_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 // eblk: if not null, the apply also writes per-block energy partials there
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,

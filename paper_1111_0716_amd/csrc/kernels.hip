@@ -255,6 +255,32 @@ __global__ __launch_bounds__(kBlock) void k_energy_batch(const PairRef* __restri
   if (threadIdx.x == 0) ebsum[slot] = tot;
 }
 
+// slots[slot] = sum of part[0..n) in a fixed order: Neumaier per thread over
+// a strided share, then the waves in order (1024 threads: the partials of a
+// batch run to tens of thousands, read once)
+constexpr int kSumBlock = 1024;
+__global__ __launch_bounds__(kSumBlock) void k_sum_slot(const double* __restrict__ part, long long n,
+                                                        double* __restrict__ slots, int slot) {
+  __shared__ double red[kSumBlock / 64];
+  double sum = 0.0, comp = 0.0;
+  for (long long i = threadIdx.x; i < n; i += kSumBlock) {
+    const double x = part[i];
+    const double t = sum + x;
+    comp += (fabs(sum) >= fabs(x)) ? (sum - t) + x : (x - t) + sum;
+    sum = t;
+  }
+  double v = sum + comp;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kSumBlock / 64; ++w) t += red[w];
+    slots[slot] = t;
+  }
+}
+
 __global__ void k_energy_finish(const double* __restrict__ ebsum, int first, int count, double factor,
                                 double* __restrict__ ex) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -291,11 +317,13 @@ inline Geo geo_of(const Instance& in) {
 }
 
 template <typename T>
-hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out, bool energy,
                          const double* gscale, double hscale, bool backward) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[b.inst];
-  if (in.reg) return launch_reg_apply_batch(p, b, psi, occ, out, gscale, hscale, backward);
+  if (in.reg)
+    return launch_reg_apply_batch(p, b, psi, occ, out, gscale, hscale, backward,
+                                  energy && reg_apply_energy(p, b.inst));
   const Geo g = geo_of(in);
   const C* tw = reinterpret_cast<const C*>(p.ws + p.tw_off);
   const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
@@ -421,9 +449,9 @@ hipError_t prepare_kernels(fock_precision prec, size_t* max_lds) {
 }
 
 hipError_t launch_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                              const double* gscale, double hscale, bool backward) {
-  return p.io64() ? apply_batch_t<double>(p, b, psi, occ, out, gscale, hscale, backward)
-                             : apply_batch_t<float>(p, b, psi, occ, out, gscale, hscale, backward);
+                              bool energy, const double* gscale, double hscale, bool backward) {
+  return p.io64() ? apply_batch_t<double>(p, b, psi, occ, out, energy, gscale, hscale, backward)
+                  : apply_batch_t<float>(p, b, psi, occ, out, energy, gscale, hscale, backward);
 }
 
 hipError_t launch_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
@@ -438,6 +466,24 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
                      reinterpret_cast<const double*>(p.ws + p.epart_off), occ,
                      reinterpret_cast<const double*>(p.ws + in.kw_off), in.nbands,
                      reinterpret_cast<double*>(p.ws + p.ebsum_off), b.slot);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_slot(const Plan& p, long long n, int slot) {
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
+  hipLaunchKernelGGL(k_sum_slot, dim3(1), dim3(kSumBlock), 0, p.stream, reinterpret_cast<const double*>(p.ws + p.epart_off),
+                     n, reinterpret_cast<double*>(p.ws + p.ebsum_off), slot);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
+  return hipGetLastError();
+}
+
+hipError_t launch_aslot_finish(const Plan& p, int inst, double* ex) {
+  const Instance& in = p.inst[inst];
+  const double factor = -0.5 * in.omega / static_cast<double>(in.npts);  // as in launch_energy_finish
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
+  hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(64), 0, p.stream,
+                     reinterpret_cast<const double*>(p.ws + p.ebsum_off), in.first_aslot, in.n_aslot, factor, ex);
   p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
   return hipGetLastError();
 }

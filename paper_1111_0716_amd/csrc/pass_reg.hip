@@ -137,9 +137,11 @@ __device__ __forceinline__ unsigned opaque(unsigned v) {
   return v;
 }
 
-// x[j] *= u[j * stride] at the lane's byte offset o, j < L (u wave-uniform)
-template <typename C, typename T, int L>
-__device__ __forceinline__ void mul_table_line_u(C* x, const T* __restrict__ u, unsigned o, size_t stride) {
+// x[j] *= u[j * stride] at the lane's byte offset o, j < L (u wave-uniform);
+// EN: also *es += u |x|^2 in FP64, taken before the multiply
+template <typename C, typename T, int L, bool EN = false>
+__device__ __forceinline__ void mul_table_line_u(C* x, const T* __restrict__ u, unsigned o, size_t stride,
+                                                 double* es = nullptr) {
   constexpr int B = batch_of(L, kRegB);
   constexpr int NB = L / B;
   T vb[2][B];
@@ -153,8 +155,26 @@ __device__ __forceinline__ void mul_table_line_u(C* x, const T* __restrict__ u, 
     }
     reg_fence();
 #pragma unroll
-    for (int j = 0; j < B; ++j) x[n * B + j] = cscale(x[n * B + j], vb[n & 1][j]);
+    for (int j = 0; j < B; ++j) {
+      if constexpr (EN) {
+        const double px = static_cast<double>(x[n * B + j].x), py = static_cast<double>(x[n * B + j].y);
+        *es += static_cast<double>(vb[n & 1][j]) * (px * px + py * py);
+      }
+      x[n * B + j] = cscale(x[n * B + j], vb[n & 1][j]);
+    }
   }
+}
+
+// Block sum of the energy partials e of the 256 threads, times the pair
+// weight w, into epart[pair * gridDim.x + block] (fixed order).
+__device__ __forceinline__ void store_line_energy(double e, double w, double* __restrict__ epart) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    epart[static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x] = w * (((red[0] + red[1]) + red[2]) + red[3]);
 }
 
 // Switch a plane's axis: thread `col` holds line x[i] = P[i][col]; afterwards
@@ -236,30 +256,47 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? R
 // ---------------------------------------------------------------------------
 // pencil pass, apply: FFT_1, x v_q/N, IFFT_1 on lines (c3, c2) of T
 // ---------------------------------------------------------------------------
-template <typename T, int L>
-__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_apply_reg(int ll, int nbands, int nk, int o0, int nP,
-                                                          const int2* __restrict__ parts, const int* __restrict__ qmap,
-                                                          typename cx<T>::t* __restrict__ tbuf,
-                                                          const T* __restrict__ vtab) {
+// EN: the apply also yields the pair energies (the spectrum is at hand after
+// FFT_1): w_o f_o w'_p f'_p sum v/N |P|^2 per line block into epart.
+template <typename T, int L, bool EN>
+__device__ __forceinline__ void pencil_apply_line(int l, int LL, int pi, int q, typename cx<T>::t* __restrict__ tbuf,
+                                                  const T* __restrict__ vtab, double* es) {
   using C = typename cx<T>::t;
-  const int LL = ll;  // lines per pair (N2 N3); L is the line length N1
-  const int l = blockIdx.x * 256 + threadIdx.x;  // line (c3, c2) = l
-  const int pi = blockIdx.y;
-  if (l >= LL) return;  // no barrier in this kernel
-  const int o = pi / nP, p = pi - o * nP;
-  const int ok = (o0 + o) / nbands;
-  const int q = qmap[ok * nk + parts[p].x];
   C* base = tbuf + static_cast<size_t>(pi) * LL * L;
   const unsigned lo = static_cast<unsigned>(l) * sizeof(C);
   C x[L];
 #pragma unroll
   for (int j1 = 0; j1 < L; ++j1) x[j1] = *lane_at(base + static_cast<size_t>(j1) * LL, lo);
   reg_fft<C, L, -1>(x);
-  mul_table_line_u<C, T, L>(x, vtab + static_cast<size_t>(q) * LL * L, opaque(static_cast<unsigned>(l) * sizeof(T)), LL);
+  mul_table_line_u<C, T, L, EN>(x, vtab + static_cast<size_t>(q) * LL * L,
+                                opaque(static_cast<unsigned>(l) * sizeof(T)), LL, es);
   reg_fft<C, L, +1>(x);
   const unsigned so = opaque(lo);
 #pragma unroll
   for (int j1 = 0; j1 < L; ++j1) *lane_at(base + static_cast<size_t>(j1) * LL, so) = x[j1];
+}
+
+template <typename T, int L, bool EN = false>
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_apply_reg(int ll, int nbands, int nk, int o0, int nP,
+                                                          const int2* __restrict__ parts, const int* __restrict__ qmap,
+                                                          typename cx<T>::t* __restrict__ tbuf,
+                                                          const T* __restrict__ vtab, const double* __restrict__ occ,
+                                                          const double* __restrict__ kw, double* __restrict__ epart) {
+  const int LL = ll;  // lines per pair (N2 N3); L is the line length N1
+  const int l = blockIdx.x * 256 + threadIdx.x;  // line (c3, c2) = l
+  const int pi = blockIdx.y;
+  const int o = pi / nP, p = pi - o * nP;
+  const int ok = (o0 + o) / nbands;
+  const int2 r = parts[p];
+  const int q = qmap[ok * nk + r.x];
+  if constexpr (!EN) {
+    if (l >= LL) return;  // no barrier in this variant
+    pencil_apply_line<T, L, false>(l, LL, pi, q, tbuf, vtab, nullptr);
+  } else {
+    double e = 0.0;
+    if (l < LL) pencil_apply_line<T, L, true>(l, LL, pi, q, tbuf, vtab, &e);
+    store_line_energy(e, kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y], epart);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -516,32 +553,48 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LIN
   }
 }
 
-template <typename T, int L>
-__global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_apply_split(
-    int ll, int nbands, int nk, int o0, int nP, const int2* __restrict__ parts, const int* __restrict__ qmap,
-    typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab) {
+template <typename T, int L, bool EN>
+__device__ __forceinline__ void pencil_apply_split_line(int l, int h, int LL, int pi, int q,
+                                                        typename cx<T>::t* __restrict__ tbuf,
+                                                        const T* __restrict__ vtab, double* es) {
   using C = typename cx<T>::t;
-  using Sh = SplitShape<T, L>;
-  const int LL = ll;
-  constexpr int LH = Sh::LH;
-  const int h = threadIdx.x & 1;
-  const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
-  const int pi = blockIdx.y;
-  if (l >= LL) return;  // uniform over the pair; no barrier in this kernel
-  const int o = pi / nP, p = pi - o * nP;
-  const int q = qmap[((o0 + o) / nbands) * nk + parts[p].x];
+  constexpr int LH = L / 2;
   C* base = tbuf + static_cast<size_t>(pi) * LL * L;
   const unsigned lo = (static_cast<unsigned>(h) * LL + l) * sizeof(C);
   C y[LH];
 #pragma unroll
   for (int m = 0; m < LH; ++m) y[m] = *lane_at(base + static_cast<size_t>(2 * m) * LL, lo);  // j1 = 2m + h
   split_fft_fwd<C, L>(y, h);  // y[k] at c1 = h L/2 + k
-  mul_table_line_u<C, T, LH>(y, vtab + static_cast<size_t>(q) * LL * L,
-                             opaque((static_cast<unsigned>(h) * LH * LL + l) * sizeof(T)), LL);
+  mul_table_line_u<C, T, LH, EN>(y, vtab + static_cast<size_t>(q) * LL * L,
+                                 opaque((static_cast<unsigned>(h) * LH * LL + l) * sizeof(T)), LL, es);
   split_fft_inv<C, L>(y, h);
   const unsigned so = opaque(lo);
 #pragma unroll
   for (int m = 0; m < LH; ++m) *lane_at(base + static_cast<size_t>(2 * m) * LL, so) = y[m];
+}
+
+template <typename T, int L, bool EN = false>
+__global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_apply_split(
+    int ll, int nbands, int nk, int o0, int nP, const int2* __restrict__ parts, const int* __restrict__ qmap,
+    typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab, const double* __restrict__ occ,
+    const double* __restrict__ kw, double* __restrict__ epart) {
+  using Sh = SplitShape<T, L>;
+  const int LL = ll;
+  const int h = threadIdx.x & 1;
+  const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
+  const int pi = blockIdx.y;
+  const int o = pi / nP, p = pi - o * nP;
+  const int ok = (o0 + o) / nbands;
+  const int2 r = parts[p];
+  const int q = qmap[ok * nk + r.x];
+  if constexpr (!EN) {
+    if (l >= LL) return;  // uniform over the pair; no barrier in this variant
+    pencil_apply_split_line<T, L, false>(l, h, LL, pi, q, tbuf, vtab, nullptr);
+  } else {
+    double e = 0.0;  // each lane: its half of the spectrum
+    if (l < LL) pencil_apply_split_line<T, L, true>(l, h, LL, pi, q, tbuf, vtab, &e);
+    store_line_energy(e, kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y], epart);
+  }
 }
 
 template <typename T, int L, typename TV = T>
@@ -745,16 +798,30 @@ void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void*
   }
 }
 
+// epart not null: the energy variant, weighted partials per (pair, line
+// block) into epart; returns the line blocks per pair
 template <typename T, int L>
-void launch_pencil_apply(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
-                         typename cx<T>::t* tbuf, const T* vtab) {
+int launch_pencil_apply(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
+                        typename cx<T>::t* tbuf, const T* vtab, const double* occ, const double* kw, double* epart) {
   const int ll = in.grid[1] * in.grid[2];
   if constexpr (RegPolicy<T, L>::SPLIT_PENCIL) {
-    hipLaunchKernelGGL((k_pencil_apply_split<T, L>), dim3((ll + SplitShape<T, L>::LPB - 1) / SplitShape<T, L>::LPB,
-                       b.npairs), dim3(256), 0, p.stream, ll, in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+    const int nlb = (ll + SplitShape<T, L>::LPB - 1) / SplitShape<T, L>::LPB;
+    if (epart)
+      hipLaunchKernelGGL((k_pencil_apply_split<T, L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
+                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+    else
+      hipLaunchKernelGGL((k_pencil_apply_split<T, L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
+                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+    return nlb;
   } else {
-    hipLaunchKernelGGL((k_pencil_apply_reg<T, L>), dim3((ll + 255) / 256, b.npairs), dim3(256), 0, p.stream, ll,
-                       in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab);
+    const int nlb = (ll + 255) / 256;
+    if (epart)
+      hipLaunchKernelGGL((k_pencil_apply_reg<T, L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
+                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+    else
+      hipLaunchKernelGGL((k_pencil_apply_reg<T, L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
+                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+    return nlb;
   }
 }
 
@@ -868,7 +935,7 @@ void mixed_lds_attr(int lim) {
 
 template <typename T>
 hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                       const double* gscale, double hscale, bool backward) {
+                       const double* gscale, double hscale, bool backward, bool energy) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[b.inst];
   const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
@@ -876,15 +943,22 @@ hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const dou
   const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
   const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
   C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
+  double* epart = energy ? reinterpret_cast<double*>(p.ws + p.epart_off) : nullptr;
+  int nlb = 0;
   bool ok;
   p.prof.begin(FOCK_K_PLANE, p.stream);
   ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<T, N, false>(p, b, in, psi, parts, nullptr, tbuf)));
   p.prof.end(FOCK_K_PLANE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   p.prof.begin(FOCK_K_PENCIL, p.stream);
-  ok = FOCK_REG_DISPATCH(in.grid[0], (launch_pencil_apply<T, N>(p, b, in, parts, qmap, tbuf, vtab)));
+  ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_apply<T, N>(p, b, in, parts, qmap, tbuf, vtab, occ, kw,
+                                                                       epart)));
   p.prof.end(FOCK_K_PENCIL, p.stream);
   if (!ok) return hipErrorInvalidValue;
+  if (energy) {
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot);
+    if (e != hipSuccess) return e;
+  }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
   ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale,
                                                         backward)));
@@ -1078,11 +1152,13 @@ void prepare_reg_dft_kernels(fock_precision prec, int lim) {
 }
 
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                                  const double* gscale, double hscale, bool backward) {
+                                  const double* gscale, double hscale, bool backward, bool energy) {
   if (p.prec == FOCK_MIXED) return mixed_apply_t(p, b, psi, occ, out, gscale, hscale, backward);
-  return p.prec == FOCK_C128 ? reg_apply_t<double>(p, b, psi, occ, out, gscale, hscale, backward)
-                             : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward);
+  return p.prec == FOCK_C128 ? reg_apply_t<double>(p, b, psi, occ, out, gscale, hscale, backward, energy)
+                             : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward, energy);
 }
+
+bool reg_apply_energy(const Plan& p, int inst) { return p.inst[inst].reg && p.prec != FOCK_MIXED; }
 
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
   if (p.prec == FOCK_MIXED) return mixed_energy_t(p, b, psi, occ);

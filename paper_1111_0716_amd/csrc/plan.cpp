@@ -367,6 +367,21 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     }
     max_n2 = std::max(max_n2, static_cast<size_t>(in.grid[1]));
   }
+  // apply-with-energy sum slots: one per apply batch of a register-line
+  // instance (not FOCK_MIXED), contiguous per instance
+  size_t max_apply_epairs = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& in = p->inst[i];
+    in.first_aslot = slot;
+    if (in.reg && prec != FOCK_MIXED) {
+      for (Batch& b : p->apply_batches) {
+        if (b.inst != i) continue;
+        b.eslot = slot++;
+        max_apply_epairs = std::max(max_apply_epairs, static_cast<size_t>(b.npairs));
+      }
+    }
+    in.n_aslot = slot - in.first_aslot;
+  }
   p->const_bytes = off;
   // ---- scratch ----
   p->tbuf_off = off;
@@ -379,7 +394,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   }
   off = align_up(off + p->tbuf_bytes);
   p->epart_off = off;
-  p->epart_bytes = std::max(max_epairs * max_n2, max_fused_epairs) * sizeof(double);
+  // per (pair, line block) energy partials: energy batches and apply-with-energy batches
+  p->epart_bytes = std::max(std::max(max_epairs, max_apply_epairs) * max_n2, max_fused_epairs) * sizeof(double);
   off = align_up(off + p->epart_bytes);
   p->partial_off = off;
   p->partial_bytes = max_partial;
