@@ -325,21 +325,13 @@ def ragged(args):
         return total, epairs
 
     log("one-at-a-time FP32 plans")
-    ms32, epairs = one_at_a_time("c64")
+    ms32, _ = one_at_a_time("c64")
     log("one-at-a-time FP64 plans")
     ms64, _ = one_at_a_time("c128")
-    # algorithmic bytes of a step: 4 s N per ordered pair of the apply, and
-    # 2 s N per FFT pair of the energy (swapped pairs folded) where the energy
-    # needs transforms of its own: off the whole-pair (cubic 16-32) and the
-    # register-line (N1 x L x L) paths, which take it from the apply's
-    # transforms in fock_apply_energy
-    reg_len = (24, 32, 36, 40, 48, 50, 54, 60, 64, 72)
-
-    def energy_from_apply(g):
-        return (g[0] == g[1] == g[2] and g[0] in (16, 24, 32)) or (g[1] == g[2] and g[0] in reg_len and g[1] in reg_len)
-
-    alg = sum(8 * int(np.prod(i.grid)) * (4 * i.ordered_pairs() + (0 if energy_from_apply(i.grid) else 2 * e))
-              for i, e in zip(insts, epairs))
+    # algorithmic bytes of a step: 4 s N per ordered pair of the apply (the
+    # FP32 plan takes E_x from the apply's own transforms in
+    # fock_apply_energy, so the energy adds no bytes)
+    alg = sum(8 * int(np.prod(i.grid)) * 4 * i.ordered_pairs() for i in insts)
     gbs = alg / (ms / 1e3) / 1e9
     line = {"metric": "band-pair Fock applications/s, uneven batch (48 instances), FP32 one graph vs FP64 one-at-a-time",
             "value": round(pairs / (ms / 1e3), 1), "unit": "ordered band pairs/s (apply + energy per step)",

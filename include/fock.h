@@ -144,10 +144,11 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
 
 /* fock_apply (V_x psi into vx_psi, the overlap into vmat if not NULL) and
  * fock_energy (E_x into device FP64 ex[n_inst]) in one call.  Both are sums
- * over the same band pairs of Eq. (2): on the whole-pair path the apply
- * kernel also forms each pair's energy from the spectrum it has already
- * transformed (FP64 partials per workgroup, summed in a fixed order), so no
- * transform runs twice; other paths run their energy batches after the apply.
+ * over the same band pairs of Eq. (2): the apply kernels (whole-pair kernel,
+ * or the pencil pass of the three-pass paths) also form each pair's energy
+ * from the spectrum they have already transformed (FP64 partials, summed in
+ * a fixed order), so no transform runs twice; FOCK_MIXED plans run their
+ * energy batches after the apply.
  * vx_psi and vmat come out bitwise equal to fock_apply's.  E_x agrees with
  * fock_energy's to rounding (FP64: bitwise reproducible from call to call,
  * but summed over ordered pairs where fock_energy folds swapped ones).

@@ -131,13 +131,13 @@ fock_status run_overlaps(Plan* p, const void* const* psi, void* const* vx_psi, v
   return FOCK_OK;
 }
 
-// E_x of every instance into ex[i].  after_apply: the whole-pair and the
-// register-line instances take their energy from the partials the apply just
-// wrote; the others run their energy batches.
+// E_x of every instance into ex[i].  after_apply: every instance but the
+// FOCK_MIXED ones takes its energy from the partials the apply just wrote;
+// those run their energy batches.
 fock_status run_energy(Plan* p, const void* const* psi, const double* const* occ, double* ex, bool after_apply) {
   for (const Batch& b : p->energy_batches) {
     const bool fused = p->inst[b.inst].fused;
-    if (after_apply && (fused || reg_apply_energy(*p, b.inst))) continue;
+    if (after_apply && (fused || batch_apply_energy(*p, b.inst))) continue;
     hipError_t e;
     if (fused) {
       e = launch_fused_energy(*p, b, psi[b.inst]);
@@ -151,7 +151,7 @@ fock_status run_energy(Plan* p, const void* const* psi, const double* const* occ
     const int ii = static_cast<int>(i);
     const hipError_t e = !after_apply             ? launch_energy_finish(*p, ii, ex + i)
                          : p->inst[i].fused       ? launch_eblk_finish(*p, ii, ex + i)
-                         : reg_apply_energy(*p, ii) ? launch_aslot_finish(*p, ii, ex + i)
+                         : batch_apply_energy(*p, ii) ? launch_aslot_finish(*p, ii, ex + i)
                                                   : launch_energy_finish(*p, ii, ex + i);
     if (e != hipSuccess) return hip_fail(e, "energy finish launch");
   }

@@ -171,13 +171,14 @@ bool reg_supported(fock_precision prec, const int grid[3]);
 size_t reg_lds_bytes(fock_precision prec, int L);
 void prepare_reg_kernels(fock_precision prec, int lim);
 // energy: the pencil pass also writes the batch's weighted pair energies to
-// its slot (b.eslot); only where reg_apply_energy(inst)
+// its slot (b.eslot); only where batch_apply_energy(inst)
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                                   const double* gscale, double hscale, bool backward, bool energy);
-bool reg_apply_energy(const Plan& p, int inst);
+// the instance's apply batches take its energy (three-pass paths, not FOCK_MIXED)
+bool batch_apply_energy(const Plan& p, int inst);
 // ebsum[slot] = fixed-order sum of the first n energy partials (epart)
 hipError_t launch_sum_slot(const Plan& p, long long n, int slot);
-// E_x of a register-line instance from its apply-with-energy slots
+// E_x of a three-pass instance from its apply-with-energy slots
 hipError_t launch_aslot_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);
 // eblk: if not null, the apply also writes per-block energy partials there

@@ -86,12 +86,17 @@ __global__ __launch_bounds__(kBlock) void k_fwd_plane(Geo g, const typename cx<T
 // ---------------------------------------------------------------------------
 // pencil pass, apply: FFT_1, x v_q / N, IFFT_1
 // ---------------------------------------------------------------------------
-template <typename T>
+// EN (fock_apply_energy): also w_o f_o w'_p f'_p sum v/N |P|^2 of the slab,
+// in FP64, into epart[pair * n2 + c2]
+template <typename T, bool EN = false>
 __global__ __launch_bounds__(kBlock) void k_pencil_apply(Geo g, int o0, int nP, const int2* __restrict__ parts,
                                                          const int* __restrict__ qmap,
                                                          typename cx<T>::t* __restrict__ tbuf,
                                                          const T* __restrict__ vtab,
-                                                         const typename cx<T>::t* __restrict__ tw) {
+                                                         const typename cx<T>::t* __restrict__ tw,
+                                                         const double* __restrict__ occ,
+                                                         const double* __restrict__ kw,
+                                                         double* __restrict__ epart) {
   using C = typename cx<T>::t;
   extern __shared__ unsigned char smem_raw[];
   C* s = reinterpret_cast<C*>(smem_raw);
@@ -110,11 +115,27 @@ __global__ __launch_bounds__(kBlock) void k_pencil_apply(Geo g, int o0, int nP, 
   __syncthreads();
   fft_lines<C, -1, false>(s, g.n1, g.n3, 1, g.n3, tw);  // axis 1
   const T* v = vtab + static_cast<size_t>(q) * npts + static_cast<size_t>(c2) * g.n3;
+  double en = 0.0;
   for (int e = threadIdx.x; e < tile; e += kBlock) {
     const int c1 = fdiv(e, rcp3), c3 = e - c1 * g.n3;
-    s[e] = cscale(s[e], v[static_cast<size_t>(c1) * plane + c3]);
+    const T vv = v[static_cast<size_t>(c1) * plane + c3];
+    if constexpr (EN) {
+      const double px = static_cast<double>(s[e].x), py = static_cast<double>(s[e].y);
+      en += static_cast<double>(vv) * (px * px + py * py);
+    }
+    s[e] = cscale(s[e], vv);
   }
-  __syncthreads();
+  if constexpr (EN) {
+    __shared__ double red[kBlock / 64];
+    const double tot = block_sum(en, red);  // ends with a barrier
+    if (threadIdx.x == 0) {
+      const int2 r = parts[p];
+      epart[static_cast<size_t>(pi) * g.n2 + c2] =
+          kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * g.nbands + r.y] * tot;
+    }
+  } else {
+    __syncthreads();
+  }
   fft_lines<C, +1, false>(s, g.n1, g.n3, 1, g.n3, tw);  // inverse axis 1
   for (int e = threadIdx.x; e < tile; e += kBlock) {
     const int j1 = fdiv(e, rcp3), c3 = e - j1 * g.n3;
@@ -321,9 +342,8 @@ hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const d
                          const double* gscale, double hscale, bool backward) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[b.inst];
-  if (in.reg)
-    return launch_reg_apply_batch(p, b, psi, occ, out, gscale, hscale, backward,
-                                  energy && reg_apply_energy(p, b.inst));
+  energy = energy && batch_apply_energy(p, b.inst);
+  if (in.reg) return launch_reg_apply_batch(p, b, psi, occ, out, gscale, hscale, backward, energy);
   const Geo g = geo_of(in);
   const C* tw = reinterpret_cast<const C*>(p.ws + p.tw_off);
   const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
@@ -338,9 +358,17 @@ hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const d
                      static_cast<const C*>(psi), b.o0, b.nP, parts, static_cast<const PairRef*>(nullptr), tbuf, tw);
   p.prof.end(FOCK_K_PLANE, p.stream);
   p.prof.begin(FOCK_K_PENCIL, p.stream);
-  hipLaunchKernelGGL((k_pencil_apply<T>), dim3(g.n2, b.npairs), dim3(kBlock), lds_tile, p.stream, g, b.o0, b.nP,
-                     parts, qmap, tbuf, vtab, tw);
+  if (energy)
+    hipLaunchKernelGGL((k_pencil_apply<T, true>), dim3(g.n2, b.npairs), dim3(kBlock), lds_tile, p.stream, g, b.o0,
+                       b.nP, parts, qmap, tbuf, vtab, tw, occ, kw, reinterpret_cast<double*>(p.ws + p.epart_off));
+  else
+    hipLaunchKernelGGL((k_pencil_apply<T, false>), dim3(g.n2, b.npairs), dim3(kBlock), lds_tile, p.stream, g, b.o0,
+                       b.nP, parts, qmap, tbuf, vtab, tw, occ, kw, static_cast<double*>(nullptr));
   p.prof.end(FOCK_K_PENCIL, p.stream);
+  if (energy) {
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * g.n2, b.eslot);
+    if (e != hipSuccess) return e;
+  }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
   hipLaunchKernelGGL((k_inv_plane_acc<T>), dim3(g.n1, b.nO), dim3(kBlock), lds_plane, p.stream, g, b.o0, b.nP,
                      parts, static_cast<const C*>(tbuf), static_cast<const C*>(psi), occ, kw, static_cast<C*>(out),
@@ -381,7 +409,8 @@ template <typename T>
 void allow_large_lds(int lim) {
   const void* fs[] = {reinterpret_cast<const void*>(&k_fwd_plane<T, false>),
                       reinterpret_cast<const void*>(&k_fwd_plane<T, true>),
-                      reinterpret_cast<const void*>(&k_pencil_apply<T>),
+                      reinterpret_cast<const void*>(&k_pencil_apply<T, false>),
+                      reinterpret_cast<const void*>(&k_pencil_apply<T, true>),
                       reinterpret_cast<const void*>(&k_pencil_energy<T>),
                       reinterpret_cast<const void*>(&k_inv_plane_acc<T>)};
   for (const void* f : fs) {
@@ -469,6 +498,8 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
   p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
   return hipGetLastError();
 }
+
+bool batch_apply_energy(const Plan& p, int inst) { return !p.inst[inst].fused && p.prec != FOCK_MIXED; }
 
 hipError_t launch_sum_slot(const Plan& p, long long n, int slot) {
   p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);

@@ -1158,7 +1158,6 @@ hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi
                              : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward, energy);
 }
 
-bool reg_apply_energy(const Plan& p, int inst) { return p.inst[inst].reg && p.prec != FOCK_MIXED; }
 
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
   if (p.prec == FOCK_MIXED) return mixed_energy_t(p, b, psi, occ);

@@ -5,7 +5,8 @@ cells, k-meshes, band counts, occupations (some zero), padded band strides,
 explicit k-pair lists and all three precisions.
 
 Each case checks V_x u (max over bands of the relative 2-norm error), E_x
-(relative) and the overlap M (max-norm relative): FP64 path <= 1e-12,
+(relative; from fock_energy and from fock_apply_energy, whose V_x u and M
+must equal fock_apply's bitwise) and the overlap M (max-norm relative): FP64 path <= 1e-12,
 FP32 and mixed paths <= 1e-5 on V_x u and M, <= 1e-6 on E_x, with the oracle
 run on the exact complex64 values upcast for the FP32 path."""
 import sys
@@ -106,7 +107,10 @@ def test_sweep_case_matches_oracle(i, device):
     occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
     (vx,), (m,) = plan.fock_apply([psi], [occ], vmat=True)
     ex = plan.fock_energy([psi], [occ]).item()
+    (vx2,), (m2,), ex2 = plan.fock_apply_energy([psi], [occ], vmat=True)
     torch.cuda.synchronize()
+    assert torch.equal(vx2[:, :, :n], vx[:, :, :n]) and torch.equal(m2, m)  # padding is never written
+    ex2 = ex2.item()
     vx = vx[:, :, :n].cpu().numpy()
     m = m.cpu().numpy()
     plan.close()
@@ -120,8 +124,9 @@ def test_sweep_case_matches_oracle(i, device):
     ee = abs(ex - eref) / abs(eref) if eref != 0 else abs(ex)
     em = np.max(np.abs(m - mref)) / max(np.max(np.abs(mref)), 1e-300)
     log(f"  V_x {ev:.2e}  E_x {ee:.2e}  M {em:.2e}")
+    ee2 = abs(ex2 - eref) / abs(eref) if eref != 0 else abs(ex2)
     assert ev <= tol["v"]
-    assert ee <= tol["e"]
+    assert ee <= tol["e"] and ee2 <= tol["e"]
     assert em <= tol["v"]
 
 
