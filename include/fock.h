@@ -147,11 +147,10 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
  * over the same band pairs of Eq. (2): the apply kernels (whole-pair kernel,
  * or the pencil pass of the three-pass paths) also form each pair's energy
  * from the spectrum they have already transformed (FP64 partials, summed in
- * a fixed order), so no transform runs twice; FOCK_MIXED plans run their
- * energy batches after the apply.
+ * a fixed order), so no transform runs twice.
  * vx_psi and vmat come out bitwise equal to fock_apply's.  E_x agrees with
- * fock_energy's to rounding (FP64: bitwise reproducible from call to call,
- * but summed over ordered pairs where fock_energy folds swapped ones).
+ * fock_energy's to rounding (bitwise reproducible from call to call, but
+ * summed over ordered pairs where fock_energy folds swapped ones).
  * Errors as fock_apply, and FOCK_ERR_ARG if ex is NULL. */
 fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const double* const* occ,
                               void* const* vx_psi, void* const* vmat, double* ex);

@@ -131,9 +131,9 @@ fock_status run_overlaps(Plan* p, const void* const* psi, void* const* vx_psi, v
   return FOCK_OK;
 }
 
-// E_x of every instance into ex[i].  after_apply: every instance but the
-// FOCK_MIXED ones takes its energy from the partials the apply just wrote;
-// those run their energy batches.
+// E_x of every instance into ex[i].  after_apply: every instance takes its
+// energy from the partials the apply just wrote (per block of the whole-pair
+// kernel, or per apply batch of the three-pass paths).
 fock_status run_energy(Plan* p, const void* const* psi, const double* const* occ, double* ex, bool after_apply) {
   for (const Batch& b : p->energy_batches) {
     const bool fused = p->inst[b.inst].fused;

@@ -174,7 +174,7 @@ void prepare_reg_kernels(fock_precision prec, int lim);
 // its slot (b.eslot); only where batch_apply_energy(inst)
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                                   const double* gscale, double hscale, bool backward, bool energy);
-// the instance's apply batches take its energy (three-pass paths, not FOCK_MIXED)
+// the instance's apply batches take its energy (the three-pass paths)
 bool batch_apply_energy(const Plan& p, int inst);
 // ebsum[slot] = fixed-order sum of the first n energy partials (epart)
 hipError_t launch_sum_slot(const Plan& p, long long n, int slot);

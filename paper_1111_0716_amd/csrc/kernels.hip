@@ -499,7 +499,7 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
   return hipGetLastError();
 }
 
-bool batch_apply_energy(const Plan& p, int inst) { return !p.inst[inst].fused && p.prec != FOCK_MIXED; }
+bool batch_apply_energy(const Plan& p, int inst) { return !p.inst[inst].fused; }
 
 hipError_t launch_sum_slot(const Plan& p, long long n, int slot) {
   p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);

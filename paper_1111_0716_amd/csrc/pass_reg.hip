@@ -715,21 +715,11 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
 // mixed precision (FOCK_MIXED): pencil pass from the FP32 pair buffer to the
 // FP64 one: forward axis 1 in FP32, kernel multiply and inverse in FP64
 // ---------------------------------------------------------------------------
-template <int L>
-__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nbands, int nk, int o0, int nP,
-                                                               const int2* __restrict__ parts,
-                                                               const int* __restrict__ qmap,
-                                                               const float2* __restrict__ t32,
-                                                               double2* __restrict__ t64,
-                                                               const double* __restrict__ vtab) {
-  const int LL = ll;
-  constexpr int LH = L / 2, LPB = 128;
-  const int h = threadIdx.x & 1;
-  const int l = blockIdx.x * LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
-  const int pi = blockIdx.y;
-  if (l >= LL) return;  // uniform over the pair; no barrier in this kernel
-  const int o = pi / nP, p = pi - o * nP;
-  const int q = qmap[((o0 + o) / nbands) * nk + parts[p].x];
+template <int L, bool EN>
+__device__ __forceinline__ void pencil_apply_mixed_line(int l, int h, int LL, int pi, int q,
+                                                        const float2* __restrict__ t32, double2* __restrict__ t64,
+                                                        const double* __restrict__ vtab, double* es) {
+  constexpr int LH = L / 2;
   const size_t base = static_cast<size_t>(pi) * LL * L;
   const unsigned le = static_cast<unsigned>(h) * LL + l;  // lane's element offset
   double2 y[LH];
@@ -741,12 +731,43 @@ __global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nband
 #pragma unroll
     for (int k = 0; k < LH; ++k) y[k] = cvt<double2>(f[k]);
   }
-  mul_table_line_u<double2, double, LH>(y, vtab + static_cast<size_t>(q) * LL * L,
-                                        opaque((static_cast<unsigned>(h) * LH * LL + l) * 8u), LL);
+  mul_table_line_u<double2, double, LH, EN>(y, vtab + static_cast<size_t>(q) * LL * L,
+                                            opaque((static_cast<unsigned>(h) * LH * LL + l) * 8u), LL, es);
   split_fft_inv<double2, L>(y, h);
   const unsigned so = opaque(le * 16u);
 #pragma unroll
   for (int m = 0; m < LH; ++m) *lane_at(t64 + base + static_cast<size_t>(2 * m) * LL, so) = y[m];
+}
+
+// EN: the energy variant (see k_pencil_apply_reg), from the FP32 forward
+// spectrum widened to FP64
+template <int L, bool EN = false>
+__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nbands, int nk, int o0, int nP,
+                                                               const int2* __restrict__ parts,
+                                                               const int* __restrict__ qmap,
+                                                               const float2* __restrict__ t32,
+                                                               double2* __restrict__ t64,
+                                                               const double* __restrict__ vtab,
+                                                               const double* __restrict__ occ,
+                                                               const double* __restrict__ kw,
+                                                               double* __restrict__ epart) {
+  const int LL = ll;
+  constexpr int LPB = 128;
+  const int h = threadIdx.x & 1;
+  const int l = blockIdx.x * LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
+  const int pi = blockIdx.y;
+  const int o = pi / nP, p = pi - o * nP;
+  const int ok = (o0 + o) / nbands;
+  const int2 r = parts[p];
+  const int q = qmap[ok * nk + r.x];
+  if constexpr (!EN) {
+    if (l >= LL) return;  // uniform over the pair; no barrier in this variant
+    pencil_apply_mixed_line<L, false>(l, h, LL, pi, q, t32, t64, vtab, nullptr);
+  } else {
+    double e = 0.0;
+    if (l < LL) pencil_apply_mixed_line<L, true>(l, h, LL, pi, q, t32, t64, vtab, &e);
+    store_line_energy(e, kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y], epart);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -892,11 +913,18 @@ struct MixedPolicy {
 };
 
 template <int L>
-void launch_pencil_mixed(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
-                         const float2* t32, double2* t64, const double* vtab) {
+int launch_pencil_mixed(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
+                        const float2* t32, double2* t64, const double* vtab, const double* occ, const double* kw,
+                        double* epart) {
   const int ll = in.grid[1] * in.grid[2];
-  hipLaunchKernelGGL((k_pencil_apply_mixed<L>), dim3((ll + 127) / 128, b.npairs), dim3(256), 0, p.stream, ll,
-                     in.nbands, in.nk, b.o0, b.nP, parts, qmap, t32, t64, vtab);
+  const int nlb = (ll + 127) / 128;
+  if (epart)
+    hipLaunchKernelGGL((k_pencil_apply_mixed<L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, in.nbands,
+                       in.nk, b.o0, b.nP, parts, qmap, t32, t64, vtab, occ, kw, epart);
+  else
+    hipLaunchKernelGGL((k_pencil_apply_mixed<L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, in.nbands,
+                       in.nk, b.o0, b.nP, parts, qmap, t32, t64, vtab, occ, kw, epart);
+  return nlb;
 }
 
 template <int L>
@@ -989,7 +1017,7 @@ hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const do
 }
 
 hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
-                         const double* gscale, double hscale, bool backward) {
+                         const double* gscale, double hscale, bool backward, bool energy) {
   const Instance& in = p.inst[b.inst];
   const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
   const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
@@ -997,15 +1025,22 @@ hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const d
   const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
   float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
   double2* t64 = reinterpret_cast<double2*>(p.ws + p.tbuf64_off);
+  double* epart = energy ? reinterpret_cast<double*>(p.ws + p.epart_off) : nullptr;
+  int nlb = 0;
   bool ok;
   p.prof.begin(FOCK_K_PLANE, p.stream);
   ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<float, N, false, double>(p, b, in, psi, parts, nullptr, t32)));
   p.prof.end(FOCK_K_PLANE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   p.prof.begin(FOCK_K_PENCIL, p.stream);
-  ok = FOCK_REG_DISPATCH(in.grid[0], (launch_pencil_mixed<N>(p, b, in, parts, qmap, t32, t64, vtab)));
+  ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_mixed<N>(p, b, in, parts, qmap, t32, t64, vtab, occ, kw,
+                                                                      epart)));
   p.prof.end(FOCK_K_PENCIL, p.stream);
   if (!ok) return hipErrorInvalidValue;
+  if (energy) {
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot);
+    if (e != hipSuccess) return e;
+  }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
   ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc<double, N>(p, b, in, parts, t64, psi, occ, kw, out, gscale, hscale,
                                                              backward)));
@@ -1153,7 +1188,7 @@ void prepare_reg_dft_kernels(fock_precision prec, int lim) {
 
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                                   const double* gscale, double hscale, bool backward, bool energy) {
-  if (p.prec == FOCK_MIXED) return mixed_apply_t(p, b, psi, occ, out, gscale, hscale, backward);
+  if (p.prec == FOCK_MIXED) return mixed_apply_t(p, b, psi, occ, out, gscale, hscale, backward, energy);
   return p.prec == FOCK_C128 ? reg_apply_t<double>(p, b, psi, occ, out, gscale, hscale, backward, energy)
                              : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward, energy);
 }

@@ -368,12 +368,12 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     max_n2 = std::max(max_n2, static_cast<size_t>(in.grid[1]));
   }
   // apply-with-energy sum slots: one per apply batch of a three-pass
-  // instance (not FOCK_MIXED), contiguous per instance
+  // instance, contiguous per instance
   size_t max_apply_epairs = 0;
   for (int i = 0; i < n_inst; ++i) {
     Instance& in = p->inst[i];
     in.first_aslot = slot;
-    if (!in.fused && prec != FOCK_MIXED) {
+    if (!in.fused) {
       for (Batch& b : p->apply_batches) {
         if (b.inst != i) continue;
         b.eslot = slot++;

@@ -380,8 +380,7 @@ def test_zero_occupations_give_zero_exchange(grid, prec, device):
                                                 ((20, 18, 24), (1, 2, 1), 2, "c64")])
 def test_apply_energy_matches_apply_and_energy(grid, kmesh, nb, prec, device):
     """fock_apply_energy: V_x u and the overlap bitwise equal to fock_apply's,
-    E_x equal to fock_energy's to rounding (bitwise on the mixed path, which
-    runs its energy batches after the apply) and to the oracle within the
+    E_x equal to fock_energy's to rounding and to the oracle within the
     path's tolerance."""
     import torch
 
@@ -401,10 +400,7 @@ def test_apply_energy_matches_apply_and_energy(grid, kmesh, nb, prec, device):
     torch.cuda.synchronize()
     assert torch.equal(v1, v0) and torch.equal(m1, m0)
     assert torch.equal(v2, v1) and torch.equal(m2, m1) and ex2.item() == e1
-    if prec != "mixed":
-        assert abs(e1 - e0) <= (1e-13 if prec == "c128" else 1e-7) * abs(e0)
-    else:
-        assert e1 == e0
+    assert abs(e1 - e0) <= (1e-13 if prec == "c128" else 1e-7) * abs(e0)
     o = Oracle.from_instance(inst)
     _, eref = o.apply(inst.psi.astype(dt).astype(np.complex128), inst.occ)
     tol = TOL["c128"]["e"] if prec == "c128" else TOL["c64"]["e"]
