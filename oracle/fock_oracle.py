@@ -288,8 +288,20 @@ class Oracle:
         psi = np.asarray(psi).astype(np.complex128)
         return self.dv * np.einsum("kin,kjn->kij", np.conj(psi), vx)
 
+    def pairs_symmetric(self):
+        """True when every listed (k, k') has its swap (k', k) listed."""
+        s = set(self.kpairs)
+        return all((b, a) in s for (a, b) in s)
+
     def gradient(self, psi, occ, vx=None, torch_convention=True):
-        """dE_x/d conj(u) = dV w f V_x u; torch's convention doubles it."""
+        """dE_x/d conj(u) = dV w f V_x u; torch's convention doubles it.
+
+        The formula differentiates Eq. (2)'s double sum only when the k-pair
+        list is closed under swapping (k, k') -> (k', k): each pair then
+        appears once with (k, n) as output and once with it as partner, and
+        both give the same term.  Other lists raise ValueError."""
+        if not self.pairs_symmetric():
+            raise ValueError("dE_x/du* = dV w f V_x u needs a k-pair list closed under swapping")
         if vx is None:
             vx, _ = self.apply(psi, occ)
         g = self.dv * self.kweight[:, None, None] * np.asarray(occ)[:, :, None] * vx

@@ -28,6 +28,20 @@ def read_golden(name):
     return out
 
 
+def cartesian_wavevector(lattice, x):
+    """The Cartesian K of the plane wave exp(i K.r) whose phase advances by
+    2 pi x_i along lattice vector a_i: the solution of a_i . K = 2 pi x_i.
+    Solved directly from the lattice rows, so it does not go through the
+    oracle's reciprocal basis."""
+    return np.linalg.solve(np.asarray(lattice, dtype=np.float64), 2.0 * np.pi * np.asarray(x, dtype=np.float64))
+
+
+def triclinic_lattice():
+    """A cell with three different edges and angles: A A^T and A^T A differ,
+    so the orientation of the reciprocal basis changes every |K|."""
+    return np.array([[6.1, 0.3, -0.4], [1.2, 5.7, 0.5], [-0.8, 1.9, 6.6]])
+
+
 def plane_wave(grid, g, omega):
     j = np.indices(grid).reshape(3, -1)
     ph = sum(2.0 * np.pi * g[i] * j[i] / grid[i] for i in range(3))
@@ -175,7 +189,6 @@ def test_plane_wave_eigenvalues_on_k_mesh():
     psi = np.stack([np.stack([plane_wave(grid, gs[k, n], omega) for n in range(nb)]) for k in range(nk)])
     o = fo.Oracle(lat, grid, kfrac, kw, MU)
     vx, ex = o.apply(psi, occ)
-    b = fo.reciprocal_rows(lat)
     eps = np.zeros((nk, nb))
     for k in range(nk):
         for n in range(nb):
@@ -184,7 +197,7 @@ def test_plane_wave_eigenvalues_on_k_mesh():
                 for m in range(nb):
                     d = gs[k, n] - gs[kp, m]
                     assert np.all(2 * np.abs(d) < np.array(grid))  # no class reduction needed
-                    kc = (d + kfrac[k] - kfrac[kp]) @ b
+                    kc = cartesian_wavevector(lat, d + kfrac[k] - kfrac[kp])
                     s += kw[kp] * occ[kp, m] * fo.screened_kernel(np.array([kc @ kc]), MU)[0]
             eps[k, n] = -s / omega
     for k in range(nk):
@@ -205,6 +218,72 @@ def test_constant_kernel_special_case():
     assert np.allclose(vx, -c * dens[None, None, :] * inst.psi, rtol=0, atol=1e-13 * np.max(np.abs(vx)))
     dv = abs(np.linalg.det(inst.lattice)) / inst.npoints
     assert ex == pytest.approx(-0.5 * c * dv * np.sum(dens ** 2), rel=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# cell geometry: the reciprocal basis and rigid rotations of the cell
+# ----------------------------------------------------------------------------
+def test_reciprocal_rows_are_dual_to_the_lattice():
+    """a_i . b_j = 2 pi delta_ij, and row i of the basis is the wave vector
+    whose phase advances by 2 pi along a_i only (solved from the lattice)."""
+    lat = triclinic_lattice()
+    b = fo.reciprocal_rows(lat)
+    assert np.allclose(lat @ b.T, 2.0 * np.pi * np.eye(3), rtol=0, atol=1e-13)
+    for i in range(3):
+        assert np.allclose(b[i], cartesian_wavevector(lat, np.eye(3)[i]), rtol=0, atol=1e-13)
+
+
+def _kernel_table_cartesian_error():
+    """Largest relative gap between the oracle's table and v(|K|) with K
+    solved from the lattice, on every class of an odd grid (one
+    representative per class) of a triclinic cell at a fractional transfer."""
+    lat = triclinic_lattice()
+    grid = (5, 3, 7)
+    q = np.array([0.25, -0.5, 0.125])
+    tab = fo.kernel_table_fast(lat, grid, q, MU)
+    ref = np.empty(grid)
+    for c in np.ndindex(*grid):
+        g = np.array([ci if 2 * ci < n else ci - n for ci, n in zip(c, grid)], dtype=np.float64)
+        kc = cartesian_wavevector(lat, g + q)
+        ref[c] = fo.screened_kernel(np.array([kc @ kc]), MU)[0]
+    return float(np.max(np.abs(tab - ref)) / np.max(ref))
+
+
+def test_kernel_table_matches_cartesian_wave_vectors():
+    assert _kernel_table_cartesian_error() <= 1e-14
+
+
+def rotation_matrix(seed):
+    """A proper rotation (det +1) drawn from a seeded normal matrix."""
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def _rotation_error(inst):
+    """Relative change of E_x and V_x u when every lattice vector is turned
+    by the same rotation R (a_i -> R a_i) while the grid values of the
+    orbitals, the fractional k-points and the weights stay as they are: a
+    rigid rotation of the whole crystal, which changes no physical result."""
+    o = fo.Oracle.from_instance(inst)
+    vx, ex = o.apply(inst.psi, inst.occ)
+    r = rotation_matrix(11)
+    rot = fo.Oracle(inst.lattice @ r.T, inst.grid, inst.kfrac, inst.kweight, inst.mu)
+    vr, er = rot.apply(inst.psi, inst.occ)
+    return max(abs(er - ex) / abs(ex), float(np.max(np.abs(vr - vx)) / np.max(np.abs(vx))))
+
+
+@pytest.fixture(scope="module")
+def triclinic_instance():
+    return inputs.small_instance(grid=(6, 4, 5), kmesh=(2, 2, 1), nbands=2, seed=(104, 0),
+                                 lattice=triclinic_lattice(), full_grid=True)
+
+
+def test_rigid_rotation_of_the_cell_changes_nothing(triclinic_instance):
+    assert _rotation_error(triclinic_instance) <= 1e-13
 
 
 # ----------------------------------------------------------------------------
@@ -354,3 +433,48 @@ def test_planted_one_sided_nyquist_breaks_gradient(skewed):
     h = 1e-5
     fd = (o.energy(inst.psi + h * d, inst.occ) - o.energy(inst.psi - h * d, inst.occ)) / (2 * h)
     assert abs(fd - np.real(np.vdot(g, d))) > 1e-6 * np.linalg.norm(g)
+
+
+def test_planted_transposed_reciprocal_basis_is_caught(triclinic_instance, monkeypatch):
+    """b taken as the rows of 2 pi A^-1 instead of 2 pi A^-T: the Cartesian
+    wave-vector pin and the rigid-rotation pin both reject it."""
+    monkeypatch.setattr(fo, "reciprocal_rows",
+                        lambda lat: 2.0 * np.pi * np.linalg.inv(np.asarray(lat, dtype=np.float64)))
+    assert _kernel_table_cartesian_error() > 1e-3
+    assert _rotation_error(triclinic_instance) > 1e-3
+
+
+# ----------------------------------------------------------------------------
+# the gradient formula and the k-pair list
+# ----------------------------------------------------------------------------
+def test_gradient_formula_needs_a_symmetric_k_pair_list():
+    """dE_x/du* = dV w f V_x u needs every listed (k, k') to have its swap
+    (k', k) listed too.  For a list that is not closed under swapping, the
+    derivative of Eq. (2)'s double sum takes each pair once as output and
+    once as partner: it is the mean of the operator over the list and over
+    its transpose.  The oracle refuses the short formula there; finite
+    differences confirm the mean and reject the short formula."""
+    inst = inputs.small_instance(grid=(6, 4, 5), kmesh=(2, 1, 1), nbands=2, seed=(105, 0), full_grid=True)
+    kp = np.array([[0, 0], [0, 1], [1, 1]])
+    o = fo.Oracle.from_instance(inst, kpairs=kp)
+    with pytest.raises(ValueError):
+        o.gradient(inst.psi, inst.occ)
+    vl, _ = o.apply(inst.psi, inst.occ)
+    vt, _ = fo.Oracle.from_instance(inst, kpairs=kp[:, ::-1]).apply(inst.psi, inst.occ)
+    wf = inst.kweight[:, None, None] * inst.occ[:, :, None]
+    g_mean = o.dv * wf * (vl + vt)       # torch convention: 2 dV w f (V^L + V^T)/2
+    g_short = 2.0 * o.dv * wf * vl
+    rng = np.random.default_rng(6)
+    h = 1e-5
+    for _ in range(3):
+        d = rng.standard_normal(inst.psi.shape) + 1j * rng.standard_normal(inst.psi.shape)
+        d /= np.linalg.norm(d)
+        fd = (o.energy(inst.psi + h * d, inst.occ) - o.energy(inst.psi - h * d, inst.occ)) / (2 * h)
+        assert abs(fd - np.real(np.vdot(g_mean, d))) <= 1e-8 * np.linalg.norm(g_mean)
+        assert abs(fd - np.real(np.vdot(g_short, d))) > 1e-4 * np.linalg.norm(g_mean)
+    # a symmetric explicit list is accepted and equals the full set
+    full = np.array([[0, 0], [0, 1], [1, 0], [1, 1]])
+    o2 = fo.Oracle.from_instance(inst, kpairs=full)
+    g2 = o2.gradient(inst.psi, inst.occ)
+    g3 = fo.Oracle.from_instance(inst).gradient(inst.psi, inst.occ)
+    assert np.allclose(g2, g3, rtol=0, atol=1e-15 * np.max(np.abs(g3)))
