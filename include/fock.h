@@ -120,7 +120,8 @@ fock_status fock_workspace_size(fock_plan_t plan, size_t* bytes);
 
 /* Attach caller-owned device memory of at least fock_workspace_size bytes
  * (256-byte aligned) and upload the tables on the plan stream.  The memory
- * must stay valid until fock_destroy or the next fock_set_workspace.
+ * must stay valid until fock_destroy or the next fock_set_workspace, which
+ * also drops every recorded graph (they address the old workspace).
  * Returns FOCK_ERR_DEVICE when no GPU is usable. */
 fock_status fock_set_workspace(fock_plan_t plan, void* dev_ptr, size_t bytes);
 
@@ -159,7 +160,12 @@ fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const do
  *   grad_ex[i] * scale * w_k * f_{k,n} * (V_x u)_{k,n}
  * with grad_ex a device FP64 array [n_inst] and scale a host number; the
  * co-densities are recomputed, never stored.  dE_x/d conj(u_{k,n}) is
- * scale = Omega/N; torch's complex-gradient convention is scale = 2 Omega/N. */
+ * scale = Omega/N; torch's complex-gradient convention is scale = 2 Omega/N
+ * (instances of different Omega/N: fold it into grad_ex[i], scale = 1).
+ * The formula differentiates Eq. (2)'s double sum when every listed k-pair
+ * (k, k') has its swap (k', k) listed (the full set always does); a plan
+ * with another explicit list returns FOCK_ERR_UNSUPPORTED before any other
+ * check. */
 fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const double* const* occ,
                                  const double* grad_ex, double scale, void* const* grad_psi);
 

@@ -301,6 +301,8 @@ fock_status fock_set_workspace(fock_plan_t plan, void* dev_ptr, size_t bytes) {
     return set_error(FOCK_ERR_UNSUPPORTED, "grid needs " + std::to_string(p->lds_needed) +
                                                " bytes of LDS per workgroup; the device allows " +
                                                std::to_string(p->max_lds));
+  // recorded graphs hold the old workspace's addresses as kernel arguments
+  p->release_graphs();
   p->ws = static_cast<unsigned char*>(dev_ptr);
   p->ws_bytes = bytes;
   e = hipMemcpyAsync(p->ws, p->host_image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
@@ -390,6 +392,11 @@ fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const
                                  const double* grad_ex, double scale, void* const* grad_psi) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (!p->inst[i].symmetric)
+      return set_error(FOCK_ERR_UNSUPPORTED, "instance " + std::to_string(i) +
+                                                 ": the gradient needs a k-pair list closed under swapping (k, k') -> (k', k)");
   fock_status s = check_ready(p);
   if (s != FOCK_OK) return s;
   if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;

@@ -128,7 +128,9 @@ def make_desc(lattice, grid, kfrac, kweight=None, nbands=1, band_stride=None, mu
     d.nk = kf.shape[0]
     d.kfrac = kf.ctypes.data_as(POINTER(c_double))
     if kweight is not None:
-        kw = np.ascontiguousarray(np.asarray(kweight, dtype=np.float64))
+        kw = np.ascontiguousarray(np.asarray(kweight, dtype=np.float64).reshape(-1))
+        if kw.shape[0] != kf.shape[0]:
+            raise ValueError(f"kweight has {kw.shape[0]} entries for {kf.shape[0]} k-points")
         keep.append(kw)
         d.kweight = kw.ctypes.data_as(POINTER(c_double))
     if kpairs is not None:
@@ -168,6 +170,8 @@ class Plan:
         self.prec = PRECISIONS[precision]
         self.cdtype = torch.complex64 if precision == "c64" else torch.complex128
         self.device = torch.device(device or "cuda:0")
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
         keep = []
         descs = (FockDesc * len(instances))()
@@ -192,8 +196,20 @@ class Plan:
         size = c_size_t()
         check(lib().fock_workspace_size(self.handle, ctypes.byref(size)))
         self.workspace_bytes = size.value
-        self.workspace = torch.empty(max(size.value, 256), dtype=torch.uint8, device=self.device)
-        check(lib().fock_set_workspace(self.handle, c_void_p(self.workspace.data_ptr()), size.value))
+        self.workspace = None
+        self.set_workspace(torch.empty(max(size.value, 256), dtype=torch.uint8, device=self.device))
+
+    def set_workspace(self, buf):
+        """Attach a device buffer of at least ``workspace_bytes`` bytes (uint8,
+        256-byte aligned) as the plan's workspace; the plan keeps a reference.
+        Graphs recorded with the previous workspace are dropped."""
+        t = self.torch
+        if not (buf.is_cuda and buf.dtype == t.uint8 and buf.is_contiguous() and buf.device == self.device):
+            raise ValueError(f"workspace must be a contiguous uint8 tensor on {self.device}")
+        if buf.numel() < self.workspace_bytes or buf.data_ptr() % 256:
+            raise ValueError(f"workspace needs {self.workspace_bytes} bytes at a 256-byte aligned address")
+        check(lib().fock_set_workspace(self.handle, c_void_p(buf.data_ptr()), self.workspace_bytes))
+        self.workspace = buf
 
     def _stream_ptr(self):
         if self.stream is not None:
@@ -203,28 +219,58 @@ class Plan:
     def _sync_stream(self):
         check(lib().fock_set_stream(self.handle, c_void_p(self._stream_ptr())))
 
-    def _check_psi(self, psi, i):
-        m = self.meta[i]
+    def _check_count(self, name, seq):
+        """One entry per instance of the plan (the library reads that many pointers)."""
+        if len(seq) != len(self.meta):
+            raise ValueError(f"{name} has {len(seq)} entries; the plan has {len(self.meta)} instances")
+
+    def _check_ex(self, ex, name="ex"):
         t = self.torch
-        if not (psi.is_cuda and psi.dtype == self.cdtype and psi.is_contiguous()):
-            raise ValueError(f"psi[{i}] must be a contiguous {self.cdtype} CUDA tensor")
-        if tuple(psi.shape[:2]) != (m["nk"], m["nbands"]) or psi[0, 0].numel() != m["band_stride"]:
-            raise ValueError(f"psi[{i}] has shape {tuple(psi.shape)}, expected "
+        if not (ex.is_cuda and ex.dtype == t.float64 and ex.is_contiguous() and ex.device == self.device and
+                ex.numel() == len(self.meta)):
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device} with "
+                             f"{len(self.meta)} entries (one per instance)")
+
+    def _check_psi(self, psi, i, name="psi"):
+        m = self.meta[i]
+        if not (psi.is_cuda and psi.dtype == self.cdtype and psi.is_contiguous() and psi.device == self.device):
+            raise ValueError(f"{name}[{i}] must be a contiguous {self.cdtype} tensor on {self.device}")
+        if psi.dim() < 3 or tuple(psi.shape[:2]) != (m["nk"], m["nbands"]) or psi[0, 0].numel() != m["band_stride"]:
+            raise ValueError(f"{name}[{i}] has shape {tuple(psi.shape)}, expected "
                              f"({m['nk']}, {m['nbands']}, {m['band_stride']})")
 
     def _check_occ(self, occ, i):
         m = self.meta[i]
         if not (occ.is_cuda and occ.dtype == self.torch.float64 and occ.is_contiguous() and
-                tuple(occ.shape) == (m["nk"], m["nbands"])):
-            raise ValueError(f"occ[{i}] must be a contiguous float64 CUDA tensor of shape ({m['nk']}, {m['nbands']})")
+                occ.device == self.device and tuple(occ.shape) == (m["nk"], m["nbands"])):
+            raise ValueError(f"occ[{i}] must be a contiguous float64 tensor on {self.device} of shape "
+                             f"({m['nk']}, {m['nbands']})")
 
-    def fock_apply(self, psi, occ, out=None, vmat=False):
-        """V_x psi for every instance; returns (outputs, overlaps or None)."""
+    def _inputs(self, psi, occ):
+        """Validated per-instance lists of orbitals and occupations."""
         psi, occ = _aslist(psi), _aslist(occ)
+        self._check_count("psi", psi)
+        self._check_count("occ", occ)
         for i, (p, o) in enumerate(zip(psi, occ)):
             self._check_psi(p, i)
             self._check_occ(o, i)
-        out = [self.torch.empty_like(p) for p in psi] if out is None else _aslist(out)
+        return psi, occ
+
+    def _outputs(self, out, like, name="out"):
+        """Per-instance output grids: new tensors, or the caller's, validated
+        (distinct from the inputs, which the library rejects as aliases)."""
+        if out is None:
+            return [self.torch.empty_like(p) for p in like]
+        out = _aslist(out)
+        self._check_count(name, out)
+        for i, o in enumerate(out):
+            self._check_psi(o, i, name)
+        return out
+
+    def fock_apply(self, psi, occ, out=None, vmat=False):
+        """V_x psi for every instance; returns (outputs, overlaps or None)."""
+        psi, occ = self._inputs(psi, occ)
+        out = self._outputs(out, psi)
         mats = None
         if vmat:
             mats = [self.torch.empty((m["nk"], m["nbands"], m["nbands"]), dtype=self.cdtype, device=self.device)
@@ -238,17 +284,15 @@ class Plan:
     def fock_apply_energy(self, psi, occ, out=None, vmat=False, ex=None):
         """fock_apply and fock_energy in one call; returns (outputs, overlaps
         or None, E_x as a float64 tensor [n_inst])."""
-        psi, occ = _aslist(psi), _aslist(occ)
-        for i, (p, o) in enumerate(zip(psi, occ)):
-            self._check_psi(p, i)
-            self._check_occ(o, i)
-        out = [self.torch.empty_like(p) for p in psi] if out is None else _aslist(out)
+        psi, occ = self._inputs(psi, occ)
+        out = self._outputs(out, psi)
         mats = None
         if vmat:
             mats = [self.torch.empty((m["nk"], m["nbands"], m["nbands"]), dtype=self.cdtype, device=self.device)
                     for m in self.meta]
         if ex is None:
             ex = self.torch.empty(len(psi), dtype=self.torch.float64, device=self.device)
+        self._check_ex(ex)
         self._sync_stream()
         check(lib().fock_apply_energy(self.handle, _ptrs([p.data_ptr() for p in psi]),
                                       _ptrs([o.data_ptr() for o in occ]), _ptrs([x.data_ptr() for x in out]),
@@ -256,24 +300,23 @@ class Plan:
         return out, mats, ex
 
     def fock_energy(self, psi, occ, ex=None):
-        psi, occ = _aslist(psi), _aslist(occ)
-        for i, (p, o) in enumerate(zip(psi, occ)):
-            self._check_psi(p, i)
-            self._check_occ(o, i)
+        """E_x of every instance as a float64 tensor [n_inst]."""
+        psi, occ = self._inputs(psi, occ)
         if ex is None:
             ex = self.torch.empty(len(psi), dtype=self.torch.float64, device=self.device)
+        self._check_ex(ex)
         self._sync_stream()
         check(lib().fock_energy(self.handle, _ptrs([p.data_ptr() for p in psi]), _ptrs([o.data_ptr() for o in occ]),
                                 c_void_p(ex.data_ptr())))
         return ex
 
     def fock_energy_backward(self, psi, occ, grad_ex, scale, out=None):
-        psi, occ = _aslist(psi), _aslist(occ)
-        for i, (p, o) in enumerate(zip(psi, occ)):
-            self._check_psi(p, i)
-            self._check_occ(o, i)
+        """grad_ex[i] * scale * w_k f_kn V_x u for every instance (grad_ex: one
+        entry per instance)."""
+        psi, occ = self._inputs(psi, occ)
         g = grad_ex.to(device=self.device, dtype=self.torch.float64).contiguous().reshape(-1)
-        out = [self.torch.empty_like(p) for p in psi] if out is None else _aslist(out)
+        self._check_ex(g, "grad_ex")
+        out = self._outputs(out, psi)
         self._sync_stream()
         check(lib().fock_energy_backward(self.handle, _ptrs([p.data_ptr() for p in psi]),
                                          _ptrs([o.data_ptr() for o in occ]), c_void_p(g.data_ptr()),
@@ -284,19 +327,23 @@ class Plan:
     def _sphere(self, gidx, npw):
         """Validate the per-instance sphere tensors; returns (gidx, npw, npw_max array)."""
         gidx, npw = _aslist(gidx), _aslist(npw)
+        self._check_count("gidx", gidx)
+        self._check_count("npw", npw)
         t = self.torch
         for i, (g, n) in enumerate(zip(gidx, npw)):
             m = self.meta[i]
-            if not (g.is_cuda and g.dtype == t.int32 and g.is_contiguous() and g.dim() == 2 and g.shape[0] == m["nk"]):
+            if not (g.is_cuda and g.dtype == t.int32 and g.is_contiguous() and g.dim() == 2 and g.shape[0] == m["nk"]
+                    and g.shape[1] >= 1 and g.device == self.device):
                 raise ValueError(f"gidx[{i}] must be a contiguous int32 CUDA tensor [nk, npw_max]")
-            if not (n.is_cuda and n.dtype == t.int32 and n.is_contiguous() and tuple(n.shape) == (m["nk"],)):
+            if not (n.is_cuda and n.dtype == t.int32 and n.is_contiguous() and tuple(n.shape) == (m["nk"],) and
+                    n.device == self.device):
                 raise ValueError(f"npw[{i}] must be a contiguous int32 CUDA tensor [nk]")
         npw_max = (c_int32 * len(gidx))(*[int(g.shape[1]) for g in gidx])
         return gidx, npw, npw_max
 
     def _check_coef(self, c, i, npw_max):
         m = self.meta[i]
-        if not (c.is_cuda and c.dtype == self.cdtype and c.is_contiguous() and
+        if not (c.is_cuda and c.dtype == self.cdtype and c.is_contiguous() and c.device == self.device and
                 tuple(c.shape) == (m["nk"], m["nbands"], npw_max)):
             raise ValueError(f"coefficients[{i}] must be a contiguous {self.cdtype} CUDA tensor "
                              f"({m['nk']}, {m['nbands']}, {npw_max})")
@@ -304,13 +351,17 @@ class Plan:
     def pw_to_grid(self, coef, gidx, npw, out=None):
         """Orbitals on the grid from sphere coefficients (see fock_pw_to_grid)."""
         coef = _aslist(coef)
+        self._check_count("coef", coef)
         gidx, npw, npw_max = self._sphere(gidx, npw)
         for i, c in enumerate(coef):
             self._check_coef(c, i, npw_max[i])
-        out = [self.torch.zeros((m["nk"], m["nbands"], m["band_stride"]), dtype=self.cdtype, device=self.device)
-               for m in self.meta] if out is None else _aslist(out)
+        if out is None:
+            out = [self.torch.zeros((m["nk"], m["nbands"], m["band_stride"]), dtype=self.cdtype, device=self.device)
+                   for m in self.meta]
+        out = _aslist(out)
+        self._check_count("out", out)
         for i, o in enumerate(out):
-            self._check_psi(o, i)
+            self._check_psi(o, i, "out")
         self._sync_stream()
         check(lib().fock_pw_to_grid(self.handle, _ptrs([c.data_ptr() for c in coef]), _ptrs([g.data_ptr() for g in gidx]),
                                     _ptrs([n.data_ptr() for n in npw]), npw_max, _ptrs([o.data_ptr() for o in out])))
@@ -319,11 +370,13 @@ class Plan:
     def grid_to_pw(self, f, gidx, npw, out=None):
         """Sphere coefficients of grid functions f (f is transformed in place)."""
         f = _aslist(f)
+        self._check_count("f", f)
         gidx, npw, npw_max = self._sphere(gidx, npw)
         for i, x in enumerate(f):
-            self._check_psi(x, i)
+            self._check_psi(x, i, "f")
         out = [self.torch.empty((m["nk"], m["nbands"], npw_max[i]), dtype=self.cdtype, device=self.device)
                for i, m in enumerate(self.meta)] if out is None else _aslist(out)
+        self._check_count("out", out)
         for i, c in enumerate(out):
             self._check_coef(c, i, npw_max[i])
         self._sync_stream()
@@ -334,6 +387,8 @@ class Plan:
     def fock_apply_pw(self, coef, gidx, npw, occ, psi_work=None, vx_work=None, out=None):
         """V_x psi on the sphere; returns (coefficients, psi_work, vx_work)."""
         coef, occ = _aslist(coef), _aslist(occ)
+        self._check_count("coef", coef)
+        self._check_count("occ", occ)
         gidx, npw, npw_max = self._sphere(gidx, npw)
         t = self.torch
         for i, (c, o) in enumerate(zip(coef, occ)):
@@ -347,9 +402,11 @@ class Plan:
         psi_work = grids() if psi_work is None else _aslist(psi_work)
         vx_work = grids() if vx_work is None else _aslist(vx_work)
         out = [t.empty_like(c) for c in coef] if out is None else _aslist(out)
+        for name, seq in (("psi_work", psi_work), ("vx_work", vx_work), ("out", out)):
+            self._check_count(name, seq)
         for i in range(len(coef)):
-            self._check_psi(psi_work[i], i)
-            self._check_psi(vx_work[i], i)
+            self._check_psi(psi_work[i], i, "psi_work")
+            self._check_psi(vx_work[i], i, "vx_work")
             self._check_coef(out[i], i, npw_max[i])
         self._sync_stream()
         check(lib().fock_apply_pw(self.handle, _ptrs([c.data_ptr() for c in coef]), _ptrs([g.data_ptr() for g in gidx]),
@@ -361,8 +418,11 @@ class Plan:
     def dft3(self, data, sign, inst=0):
         """In-place unnormalised 3-D DFT of every grid in ``data`` (a contiguous
         complex tensor [..., N] of the plan precision on the instance's grid)."""
+        if not 0 <= int(inst) < len(self.meta):
+            raise ValueError(f"instance {inst} out of range (plan has {len(self.meta)})")
         m = self.meta[inst]
-        if not (data.is_cuda and data.dtype == self.cdtype and data.is_contiguous() and data.numel() % m["npts"] == 0):
+        if not (data.is_cuda and data.dtype == self.cdtype and data.is_contiguous() and data.device == self.device and
+                data.numel() % m["npts"] == 0):
             raise ValueError(f"data must be a contiguous {self.cdtype} CUDA tensor of whole grids of {m['npts']} points")
         self._sync_stream()
         check(lib().fock_dft3(self.handle, int(inst), int(sign), data.numel() // m["npts"], c_void_p(data.data_ptr()),
@@ -421,27 +481,37 @@ def _aslist(x):
 
 
 def fock_energy_autograd():
-    """torch.autograd.Function whose forward is E_x (library fock_energy) and
-    whose backward is the library's hand-written gradient kernel path
-    (fock_energy_backward), with co-densities recomputed."""
+    """torch.autograd.Function whose forward is E_x of every instance of a
+    plan (library fock_energy, a float64 tensor [n_inst]) and whose backward
+    is the library's hand-written gradient path (fock_energy_backward), with
+    co-densities recomputed.
+
+    Call as ``FockEnergy.apply(plan, occ, *psi)`` with one orbital tensor per
+    instance and ``occ`` a list of occupation tensors.  Each psi[i] receives
+    torch's complex gradient 2 dV_i grad_i w f V_x u (dV_i = Omega_i/N_i).
+    Plans whose k-pair list is not closed under swapping raise (the library
+    returns FOCK_ERR_UNSUPPORTED for their gradient)."""
     import torch
 
     class FockEnergy(torch.autograd.Function):
         @staticmethod
-        def forward(ctx, psi, occ, plan):
-            ex = plan.fock_energy(psi, occ)
-            ctx.save_for_backward(psi, occ)
+        def forward(ctx, plan, occ, *psi):
+            occ = _aslist(occ)
+            ex = plan.fock_energy(list(psi), occ)
+            ctx.save_for_backward(*psi)
             ctx.plan = plan
-            return ex[0]
+            ctx.occ = occ
+            return ex
 
         @staticmethod
         def backward(ctx, grad):
-            psi, occ = ctx.saved_tensors
+            psi = list(ctx.saved_tensors)
             plan = ctx.plan
-            m = plan.meta[0]
-            # torch's complex gradient is 2 dE/d conj(psi); dE/d conj(psi) = dV w f V_x psi
-            scale = 2.0 * m["omega"] / m["npts"]
-            g = plan.fock_energy_backward(psi, occ, grad.reshape(1), scale)[0]
-            return g, None, None
+            # torch's complex gradient is 2 dE/d conj(psi), dE/d conj(psi) = dV w f V_x psi;
+            # the per-instance factor 2 dV_i rides on grad_ex so that scale = 1
+            dv2 = torch.tensor([2.0 * m["omega"] / m["npts"] for m in plan.meta], dtype=torch.float64,
+                               device=plan.device)
+            g = plan.fock_energy_backward(psi, ctx.occ, grad.reshape(-1).to(torch.float64) * dv2, 1.0)
+            return (None, None, *g)
 
     return FockEnergy
