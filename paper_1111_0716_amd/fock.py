@@ -58,9 +58,18 @@ _lib = None
 
 
 def lib():
-    """Load libfock.so (raises if it has not been built)."""
+    """Load libfock.so (raises if it has not been built).
+
+    torch is imported first: libfock.so needs libamdhip64.so.7, and torch
+    ships its own HIP runtime under that soname.  Loaded after torch, the
+    library binds to torch's runtime, the one that owns the device memory
+    and streams it is handed; loaded before, the dynamic loader would bring
+    in the system runtime and torch a second copy, and the library's HIP
+    calls would go to a runtime torch never initialised."""
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (see above: one HIP runtime per process)
+
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)
