@@ -14,11 +14,16 @@ headline, the FP64 path is reported beside it.
 
 Per-kernel times come from HIP events the library records on its own
 stream around every launch, through the timed steps.  The roofline entry
-also quotes a measured device-to-device copy rate beside the 8 TB/s peak.
-The CPU baseline is the FP64 oracle timed on a bounded sample of pairs of
-the same workload on this host.
+rates the unit that dominates the step (the whole-pair kernel, or the three
+passes of a three-pass batch together) by the compulsory 4 s N bytes per
+ordered pair, and quotes a measured device-to-device copy rate beside the
+8 TB/s peak.  The default run also times the largest workload, the
+beta-boron-shaped 72^3 cell (1 warm-up + 3 steps, `beta_boron_fp32`).  The
+CPU baseline is the FP64 oracle timed on a bounded sample of pairs of the
+same workload on this host, with one thread and with one single-threaded
+process per usable core; `host` records the machine.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--beta-steps B]
 """
 import argparse
 import json
@@ -36,6 +41,7 @@ HBM_PEAK_GBS = 8000.0
 # copy-calibrated HBM traffic of the dominant FP32 kernel, written by
 # paper_1111_0716_amd.profile_summary from rocprofv3 counter runs of this script
 TRAFFIC_FILES = {"alpha": "profiles/{kind}_alpha_boron_32cubed_fp32_traffic.md",
+                 "beta": "profiles/{kind}_beta_boron_72cubed_fp32_traffic.md",
                  "diff": "profiles/{kind}_diff_64cubed_fp32_traffic.md"}
 WORKLOADS = {
     "2": "alpha-boron-shaped rhombohedral cell a=9.56 bohr alpha=58.0 deg, 32^3 grid, 4x4x4 k-mesh "
@@ -52,47 +58,73 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_model(grid, s):
-    """Algorithmic flops and bytes per band pair for each kernel kind.
+THREE_PASS = ("plane", "pencil", "accumulate")
+THREE_PASS_UNIT = "three-pass apply (plane + pencil + accumulate of one batch)"
 
-    Whole-pair kernels (one band pair per pass, nothing staged off chip):
-      apply   F = 10 N log2 N + 16 N,  B = 4 s N  (read u_m and u_n, read and
-              write the output once per pair: the compulsory operand traffic)
-      energy  F = 5 N log2 N + 9 N,    B = 2 s N  (read u_m and u_n)
-    Three-pass kernels (the same flops split by pass; bytes are what each pass
-    must read and write once, its pair grid included):
-      plane       F = 5 N log2(N2 N3) + 6 N,  B = 3 s N
-      pencil      F = 10 N log2 N1 + 2 N,     B = 2 s N + r N (table)
-      accumulate  F = 5 N log2(N2 N3) + 8 N,  B = 2 s N
-    with s the complex size and r the real size."""
+
+def kernel_model(grid, s):
+    """Algorithmic flops and bytes per band pair.
+
+    apply (whole-pair kernel, or the three passes of a batch together):
+        F = 10 N log2 N + 16 N,  B = 4 s N  (read u_m and u_n, read and write
+        the output once per ordered pair: the compulsory operand traffic)
+    energy (whole-pair energy kernel):
+        F = 5 N log2 N + 9 N,    B = 2 s N  (read u_m and u_n)
+    The passes of the three-pass path split the apply's flops
+        plane       F = 5 N log2(N2 N3) + 6 N
+        pencil      F = 10 N log2 N1 + 2 N
+        accumulate  F = 5 N log2(N2 N3) + 8 N
+    but carry no byte model of their own: what one pass moves depends on how
+    much of its operands the caches serve, so per-pass bytes are only quoted
+    from the hardware counters.  s is the complex size."""
     n1, n2, n3 = grid
     n = n1 * n2 * n3
-    r = s // 2
     l23 = math.log2(n2 * n3)
     l1 = math.log2(n1)
     return {
         "fused": dict(flops=10 * n * math.log2(n) + 16 * n, bytes=4 * s * n),
         "energy_fused": dict(flops=5 * n * math.log2(n) + 9 * n, bytes=2 * s * n),
-        "plane": dict(flops=5 * n * l23 + 6 * n, bytes=3 * s * n),
-        "pencil": dict(flops=10 * n * l1 + 2 * n, bytes=2 * s * n + r * n),
-        "accumulate": dict(flops=5 * n * l23 + 8 * n, bytes=2 * s * n),
-        "energy_plane": dict(flops=5 * n * l23 + 6 * n, bytes=3 * s * n),
-        "energy_pencil": dict(flops=5 * n * l1 + 3 * n, bytes=s * n + r * n),
+        "plane": dict(flops=5 * n * l23 + 6 * n),
+        "pencil": dict(flops=10 * n * l1 + 2 * n),
+        "accumulate": dict(flops=5 * n * l23 + 8 * n),
+        "energy_plane": dict(flops=5 * n * l23 + 6 * n),
+        "energy_pencil": dict(flops=5 * n * l1 + 3 * n),
     }
 
 
-def roofline(kern, stats, grid, s, peak_tflops, traffic_file=None):
-    """Roofline entry of the kernel kind with the largest share of the
-    profiled step (apply, energy and backward: apply kinds run twice)."""
+def _units(stats):
+    """Band pairs a profiled step runs through each kernel kind (the bench
+    step is one apply with energy and one backward: apply kinds run twice)."""
+    u = {k: 2 * stats["apply_fft_pairs"] for k in ("fused",) + THREE_PASS}
+    u.update({k: stats["energy_fft_pairs"] for k in ("energy_fused", "energy_plane", "energy_pencil")})
+    return u
+
+
+def dominant_apply(kern):
+    """(name, total ms, launches) of what dominates the step: the whole-pair
+    kernel, the three passes of the three-pass path taken together (one
+    launch of each per batch), or the whole-pair energy kernel."""
+    cands = []
+    for k in ("fused", "energy_fused"):
+        if kern.get(k, (0, 0))[1] > 0:
+            cands.append((k, kern[k][0], kern[k][1]))
+    if all(kern.get(k, (0, 0))[1] > 0 for k in THREE_PASS):
+        cands.append((THREE_PASS_UNIT, sum(kern[k][0] for k in THREE_PASS), kern["plane"][1]))
+    return max(cands, key=lambda c: c[1])
+
+
+def roofline(kern, stats, grid, s, peak_tflops, traffic=None):
+    """Roofline entry of the unit with the largest share of the profiled step.
+    ``traffic``: counter bytes per launch of that unit (None if not measured
+    for the current sources)."""
     model = kernel_model(grid, s)
-    units = {k: 2 * stats["apply_fft_pairs"] for k in ("fused", "plane", "pencil", "accumulate")}
-    units.update({k: stats["energy_fft_pairs"] for k in ("energy_fused", "energy_plane", "energy_pencil")})
-    cands = [k for k in model if kern.get(k, (0, 0))[1] > 0]
-    dom = max(cands, key=lambda k: kern[k][0])
-    tot_ms, launches = kern[dom]
+    units = _units(stats)
+    dom, tot_ms, launches = dominant_apply(kern)
+    mk = "energy_fused" if dom == "energy_fused" else "fused"  # the three passes are one apply
+    nunits = units["fused"] if dom == THREE_PASS_UNIT else units[dom]
     per_launch_ms = tot_ms / launches
-    flops = model[dom]["flops"] * units[dom] / launches
-    byts = model[dom]["bytes"] * units[dom] / launches
+    flops = model[mk]["flops"] * nunits / launches
+    byts = model[mk]["bytes"] * nunits / launches
     tflops = flops / (per_launch_ms * 1e-3) / 1e12
     gbs = byts / (per_launch_ms * 1e-3) / 1e9
     alu_frac = tflops / peak_tflops
@@ -103,33 +135,50 @@ def roofline(kern, stats, grid, s, peak_tflops, traffic_file=None):
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
-    traffic = None
-    if traffic_file:
-        from paper_1111_0716_amd.profile_summary import read_traffic
-        traffic = read_traffic(os.path.join(ROOT, traffic_file.format(kind=dom)), dom)
     if traffic:
         roof["traffic_gbs"] = round(traffic / (per_launch_ms * 1e-3) / 1e9, 1)
         roof["traffic_over_algorithmic"] = round(traffic / byts, 4)
     roof.update({"traffic": traffic, "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                 "copy-calibrated)", "algorithmic_bytes_per_launch": byts, "kernel": dom, "launches": launches, "launch_ms": round(per_launch_ms, 4),
-                 "units_per_launch": round(units[dom] / launches, 1),
+                 "copy-calibrated)", "algorithmic_bytes_per_launch": byts, "kernel": dom, "launches": launches,
+                 "launch_ms": round(per_launch_ms, 4), "units_per_launch": round(nunits / launches, 1),
                  "alt": {"hbm_gbs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "alu_tflops": round(tflops, 3),
                          "alu_frac": round(alu_frac, 4)}})
     return roof
 
 
+def unit_traffic(workload, dom):
+    """Counter bytes per launch of the dominant unit from the committed
+    traffic summaries (the three passes summed), or None."""
+    pattern = TRAFFIC_FILES.get(workload)
+    if not pattern:
+        return None
+    from paper_1111_0716_amd.profile_summary import read_traffic
+    kinds = THREE_PASS if dom == THREE_PASS_UNIT else (dom,)
+    vals = [read_traffic(os.path.join(ROOT, pattern.format(kind=k)), k) for k in kinds]
+    return None if any(v is None for v in vals) else sum(vals)
+
+
 def kernel_rates(kern, stats, grid, s):
-    """Achieved algorithmic GB/s and TFLOP/s of every kernel kind of a step."""
+    """Per kernel kind of a step: time, launches and achieved algorithmic
+    TFLOP/s; GB/s of the 4 s N (apply) or 2 s N (energy) model only for the
+    units that do a whole apply or energy: the whole-pair kernels and the
+    three passes together."""
     model = kernel_model(grid, s)
-    units = {k: 2 * stats["apply_fft_pairs"] for k in ("fused", "plane", "pencil", "accumulate")}
-    units.update({k: stats["energy_fft_pairs"] for k in ("energy_fused", "energy_plane", "energy_pencil")})
+    units = _units(stats)
     out = {}
     for k, (ms, n) in kern.items():
         if n == 0 or k not in model or ms <= 0:
             continue
         sec = ms * 1e-3
-        out[k] = {"ms": round(ms, 3), "launches": n, "gbs": round(model[k]["bytes"] * units[k] / sec / 1e9, 1),
-                  "tflops": round(model[k]["flops"] * units[k] / sec / 1e12, 3)}
+        out[k] = {"ms": round(ms, 3), "launches": n, "tflops": round(model[k]["flops"] * units[k] / sec / 1e12, 3)}
+        if "bytes" in model[k]:
+            out[k]["gbs"] = round(model[k]["bytes"] * units[k] / sec / 1e9, 1)
+    if all(kern.get(k, (0, 0))[1] > 0 for k in THREE_PASS):
+        ms = sum(kern[k][0] for k in THREE_PASS)
+        sec = ms * 1e-3
+        out["three_pass"] = {"ms": round(ms, 3), "launches": kern["plane"][1],
+                             "gbs": round(model["fused"]["bytes"] * units["fused"] / sec / 1e9, 1),
+                             "tflops": round(model["fused"]["flops"] * units["fused"] / sec / 1e12, 3)}
     return out
 
 
@@ -153,7 +202,7 @@ def copy_bandwidth(device, mib=1024, reps=5):
     return gbs
 
 
-def run_path(inst, prec, steps, warmup, device, profile=True):
+def run_path(inst, prec, steps, warmup, device, profile=True, breakdown=True):
     import torch
 
     from paper_1111_0716_amd import fock
@@ -211,6 +260,7 @@ def run_path(inst, prec, steps, warmup, device, profile=True):
     if profile:
         res["kernels"] = {k: (v[0] / steps, v[1] // steps) for k, v in plan.profile_read().items()}
         plan.profile(False)
+    if profile and breakdown:
         # apply-only timing (one call) for the breakdown
         plan.profile_read()  # reset
         plan.profile(True)
@@ -224,45 +274,98 @@ def run_path(inst, prec, steps, warmup, device, profile=True):
     return res
 
 
-def _oracle_sample(inst, seconds):
-    """(pairs, seconds, last n): all partners (k', m) of outputs (k=0, n), in
-    order, until `seconds` have passed."""
+def _oracle_sample(inst, seconds, outputs=None):
+    """(pairs, seconds): every partner (k', m) of each output (k, n) in
+    ``outputs`` (default: k = 0, all n), in order, until ``seconds`` have
+    passed (checked after each partner k-point)."""
     from oracle.fock_oracle import Oracle
 
     psi = inst.psi.astype(np.complex128)
     o = Oracle.from_instance(inst)
+    outputs = [(0, n) for n in range(inst.nbands)] if outputs is None else outputs
     npairs = 0
     t0 = time.perf_counter()
-    for n in range(inst.nbands):
+    for (k, n) in outputs:
         for kp in range(inst.nk):
-            v = o.v(0, kp)
+            v = o.v(k, kp)
             for m in range(inst.nbands):
-                o.pair(psi[0, n], psi[kp, m], v)
+                o.pair(psi[k, n], psi[kp, m], v)
                 npairs += 1
             if time.perf_counter() - t0 > seconds:
-                return npairs, time.perf_counter() - t0, n
-    return npairs, time.perf_counter() - t0, inst.nbands - 1
+                return npairs, time.perf_counter() - t0
+    return npairs, time.perf_counter() - t0
 
 
-def cpu_baseline(inst, seconds, seconds_1t=5.0):
-    """FP64 oracle on a bounded sample of the workload, with every BLAS thread
-    of the host, and (beside it) with one thread."""
-    threads = os.cpu_count() or 1
-    single = None
+_SAMPLE = {}
+
+
+def _oracle_worker(args):
+    """One process of the all-core sample: outputs (k, n) with
+    (k N_b + n) mod workers == rank, one BLAS thread."""
+    rank, workers, seconds = args
+    from threadpoolctl import threadpool_limits
+
+    inst = _SAMPLE["inst"]
+    outs = [(k, n) for k in range(inst.nk) for n in range(inst.nbands) if (k * inst.nbands + n) % workers == rank]
+    with threadpool_limits(limits=1):
+        return _oracle_sample(inst, seconds, outs)
+
+
+def cpu_baseline(inst, seconds, seconds_1t=5.0, max_workers=16):
+    """The FP64 oracle on a bounded sample of the workload: one process with
+    one thread, then one single-threaded process per usable core (at most
+    ``max_workers``), each on its own output bands, for about ``seconds``.
+    Band pairs are independent and of equal cost, so the all-core rate is
+    the pairs of all processes over the slowest one's time.  Runs before the
+    GPU is touched (the pool forks this process)."""
+    import multiprocessing
+
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        p1, t1 = _oracle_sample(inst, seconds_1t)
+    single = {"value": round(p1 / t1, 2), "cores": 1, "sample": f"{p1} ordered pairs (outputs k=0) in {t1:.1f} s"}
+    workers = max(1, min(len(os.sched_getaffinity(0)), max_workers))
+    _SAMPLE["inst"] = inst
+    ctx = multiprocessing.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_worker, [(r, workers, seconds) for r in range(workers)])
+    wall = time.perf_counter() - t0
+    _SAMPLE.clear()
+    pairs = sum(r[0] for r in res)
+    slowest = max(r[1] for r in res)
+    return dict(value=round(pairs / slowest, 2), unit="ordered band pairs/s (apply + energy per pair, FP64 oracle)",
+                cores=workers, kind="oracle",
+                sample=f"{pairs} ordered pairs over {workers} single-threaded processes, each on its own output bands "
+                       f"(every k', m per output), {slowest:.1f} s each ({wall:.1f} s wall with start-up)",
+                single_thread=single)
+
+
+def host_info():
+    """What the numbers were measured on."""
+    info = {"nproc": os.cpu_count(), "cpus_usable": len(os.sched_getaffinity(0))}
     try:
-        from threadpoolctl import threadpool_info, threadpool_limits
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-        with threadpool_limits(limits=1):
-            p1, t1, _ = _oracle_sample(inst, seconds_1t)
-        single = {"value": p1 / t1, "cores": 1, "sample": f"{p1} ordered pairs in {t1:.1f} s"}
+        with open("/proc/cpuinfo") as f:
+            names = [l.split(":", 1)[1].strip() for l in f if l.startswith("model name")]
+        info["cpu_model"] = names[0] if names else None
+    except OSError:
+        info["cpu_model"] = None
+    try:
+        with open("/opt/rocm/.info/version") as f:
+            info["rocm"] = f.read().strip()
+    except OSError:
+        info["rocm"] = None
+    try:
+        import torch
+
+        info["torch"] = torch.__version__
+        info["torch_hip"] = torch.version.hip
+        if torch.cuda.is_available():
+            info["gpu"] = torch.cuda.get_device_name(0)
     except ImportError:
         pass
-    npairs, el, n = _oracle_sample(inst, seconds)
-    out = dict(value=npairs / el, unit="ordered band pairs/s (apply+energy per pair, FP64)", cores=threads,
-               kind="oracle", sample=f"{npairs} ordered pairs (outputs k=0, n<= {n}; every k', m) in {el:.1f} s")
-    if single:
-        out["single_thread"] = single
-    return out
+    return info
 
 
 def ragged(args):
@@ -549,6 +652,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--beta-steps", type=int, default=3,
+                    help="timed steps of the beta-boron 72^3 leg of the default run (0: skip it)")
     ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw", "precision"], default="alpha")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (the reference dispatch "
@@ -577,6 +682,12 @@ def main():
     log(f"generating inputs: preset {cfg} ({WORKLOADS[cfg]})")
     inst = inputs.config(cfg, dtype=np.complex128, workers=16)
     inst32 = inst.astype(np.complex64)
+    cb = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the sample's process pool forks this process
+        log(f"CPU baseline: FP64 oracle, one thread for ~5 s, then every usable core for ~{args.cpu_seconds:.0f} s")
+        cb = cpu_baseline(inst, args.cpu_seconds)
+        log(f"  {cb['value']} pairs/s on {cb['cores']} cores ({cb['single_thread']['value']} on one)")
     if args.copy_calibration_mib:
         nbytes = args.copy_calibration_mib << 20
         src = torch.ones(nbytes, dtype=torch.uint8, device=device)
@@ -600,9 +711,9 @@ def main():
 
     pairs = r32["stats"]["ordered_pairs"]
     value = pairs / (r32["ms_per_step"] / 1e3)
-
+    dom = dominant_apply(r32["kernels"])[0]
     roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
-                    traffic_file=TRAFFIC_FILES.get(args.workload))
+                    traffic=unit_traffic(args.workload, dom))
     copy_gbs = copy_bandwidth(device)
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["hbm_frac_vs_copy"] = round(roof["alt"]["hbm_gbs"] / copy_gbs, 4)
@@ -637,11 +748,34 @@ def main():
                         "apply_ms": round(sum(v[0] for v in r64["apply_kernels"].values()), 3)}
         line["fp32_speedup_over_fp64"] = round(r64["ms_per_step"] / r32["ms_per_step"], 3)
         line["ex_fp32_vs_fp64_rel"] = abs(r32["ex"] - r64["ex"]) / abs(r64["ex"])
-    if not args.no_cpu_baseline:
-        log(f"CPU baseline: FP64 oracle for ~{args.cpu_seconds:.0f} s")
-        cb = cpu_baseline(inst, args.cpu_seconds)
+    del inst, inst32
+    if args.workload == "alpha" and args.beta_steps > 0:
+        line["beta_boron_fp32"] = beta_leg(args, device)
+    if cb:
         line["cpu_baseline"] = cb
+    line["host"] = host_info()
     print(json.dumps(line), flush=True)
+
+
+def beta_leg(args, device):
+    """The largest workload (beta-boron-shaped 72^3, 2x2x2 k-mesh, 160 bands)
+    on the FP32 path, timed like the headline: fock_apply_energy + backward
+    per step, the three-pass apply rated on the 4 s N model."""
+    from paper_1111_0716_amd import inputs
+
+    log(f"beta-boron leg: generating inputs ({WORKLOADS['3']})")
+    inst = inputs.config("3", dtype=np.complex64, workers=16)
+    w = min(1, args.warmup)
+    log(f"beta-boron FP32 path: {w} warm-up + {args.beta_steps} timed steps")
+    r = run_path(inst, "c64", args.beta_steps, w, device, breakdown=False)
+    log(f"  {r['ms_per_step']:.1f} ms/step")
+    pairs = r["stats"]["ordered_pairs"]
+    dom = dominant_apply(r["kernels"])[0]
+    roof = roofline(r["kernels"], r["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"], traffic=unit_traffic("beta", dom))
+    return {"workload": WORKLOADS["3"], "ordered_pairs_per_step": pairs, "steps": args.beta_steps, "warmup": w,
+            "ms_per_step": round(r["ms_per_step"], 3), "pairs_per_s": round(pairs / (r["ms_per_step"] / 1e3), 1),
+            "roofline": roof, "kernels_ms": {k: round(v[0], 3) for k, v in r["kernels"].items() if v[1]},
+            "kernel_rates": kernel_rates(r["kernels"], r["stats"], inst.grid, 8)}
 
 
 if __name__ == "__main__":

@@ -18,9 +18,10 @@ def test_apply_model_per_pair(L, flops_m, bytes_mb32):
     # the reference figures carry 2-4 significant digits
     assert m["fused"]["flops"] / 1e6 == pytest.approx(flops_m, rel=1e-2)
     assert m["fused"]["bytes"] / 1e6 == pytest.approx(bytes_mb32, rel=1e-2)
-    # the three-pass split adds up to the same flops
+    # the three-pass split adds up to the same flops, and the passes carry no byte model
     split = m["plane"]["flops"] + m["pencil"]["flops"] + m["accumulate"]["flops"]
     assert split == pytest.approx(m["fused"]["flops"], rel=1e-12)
+    assert all("bytes" not in m[k] for k in bench.THREE_PASS)
     # the energy path is the forward half
     n = L ** 3
     assert m["energy_fused"]["flops"] == pytest.approx(5 * n * math.log2(n) + 9 * n)
@@ -40,3 +41,47 @@ def test_roofline_picks_dominant_kernel_and_bound():
     rates = bench.kernel_rates(kern, stats, (32, 32, 32), 8)
     assert set(rates) == {"fused", "energy_fused"}
     assert rates["fused"]["gbs"] == pytest.approx(gbs, rel=1e-3)  # two launches of the same size
+
+
+def test_three_pass_apply_is_rated_as_one_unit():
+    """The three passes of a batch are one apply: 4 s N per ordered pair over
+    their summed time, never a per-pass byte figure (which caches can push
+    above the peak)."""
+    stats = {"apply_fft_pairs": 1_638_400, "energy_fft_pairs": 0}
+    kern = {"plane": (2 * 2650.0, 2 * 1215), "pencil": (2 * 2040.0, 2 * 1215), "accumulate": (2 * 2350.0, 2 * 1215),
+            "overlap": (17.0, 1)}
+    r = bench.roofline(kern, stats, (72, 72, 72), 8, 78.6)
+    assert r["kernel"] == bench.THREE_PASS_UNIT and r["launches"] == 2 * 1215
+    per_launch_s = (2650.0 + 2040.0 + 2350.0) / 1215 * 1e-3
+    pairs_per_launch = 2 * 1_638_400 / (2 * 1215)
+    gbs = 4 * 8 * 72 ** 3 * pairs_per_launch / per_launch_s / 1e9
+    assert r["alt"]["hbm_gbs"] == pytest.approx(gbs, rel=1e-3)
+    assert r["frac"] <= 1.0
+    rates = bench.kernel_rates(kern, stats, (72, 72, 72), 8)
+    assert "gbs" not in rates["plane"] and "gbs" not in rates["pencil"] and "gbs" not in rates["accumulate"]
+    assert rates["three_pass"]["gbs"] == pytest.approx(gbs, rel=1e-3)
+
+
+def test_whole_pair_kernel_dominates_when_larger():
+    stats = {"apply_fft_pairs": 1000, "energy_fft_pairs": 0}
+    kern = {"fused": (100.0, 2), "plane": (10.0, 4), "pencil": (10.0, 4), "accumulate": (10.0, 4)}
+    assert bench.dominant_apply(kern)[0] == "fused"
+    kern["plane"] = (90.0, 4)
+    assert bench.dominant_apply(kern)[0] == bench.THREE_PASS_UNIT
+
+
+def test_cpu_baseline_uses_every_usable_core_on_a_tiny_instance():
+    """The all-core sample forks one single-threaded oracle process per core
+    (capped), each on its own outputs, and reports the processes it used."""
+    from paper_1111_0716_amd import inputs
+
+    inst = inputs.small_instance(grid=(8, 6, 8), kmesh=(2, 1, 1), nbands=3, seed=(700, 0), full_grid=True)
+    cb = bench.cpu_baseline(inst, seconds=0.5, seconds_1t=0.2, max_workers=3)
+    assert cb["kind"] == "oracle" and cb["value"] > 0
+    assert cb["cores"] == min(3, len(os.sched_getaffinity(0)))
+    assert cb["single_thread"]["cores"] == 1
+
+
+def test_host_info_fields():
+    h = bench.host_info()
+    assert h["nproc"] >= 1 and h["cpus_usable"] >= 1 and "cpu_model" in h and "rocm" in h
