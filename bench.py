@@ -94,8 +94,14 @@ def kernel_model(grid, s):
 
 def _units(stats):
     """Band pairs a profiled step runs through each kernel kind (the bench
-    step is one apply with energy and one backward: apply kinds run twice)."""
-    u = {k: 2 * stats["apply_fft_pairs"] for k in ("fused",) + THREE_PASS}
+    step is one apply with energy and one backward: apply kinds run twice).
+    An apply serves every ordered pair (the whole-pair kernel and the three
+    passes taken together are rated per ordered pair); with pair symmetry the
+    plane and pencil passes transform each unordered pair once
+    (apply_fft_pairs), while the accumulate and mirror passes still do one
+    inverse transform and accumulate per ordered pair."""
+    u = {k: 2 * stats["ordered_pairs"] for k in ("fused", "accumulate")}
+    u.update({k: 2 * stats["apply_fft_pairs"] for k in ("plane", "pencil")})
     u.update({k: stats["energy_fft_pairs"] for k in ("energy_fused", "energy_plane", "energy_pencil")})
     return u
 

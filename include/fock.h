@@ -102,13 +102,21 @@ fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision pre
  *                   |O| x |P| pairs per batch
  *   fused_split     whole-pair path: partner slices per output (1..4)
  *   no_fused        1: use the three-pass path for every grid
+ *   no_pair_symmetry 1: three-pass register-line path transforms every
+ *                   ordered pair; 0: with the full k-pair set it transforms
+ *                   each unordered pair once, W_nm(k,k') = conj W_mn(k',k)
+ *                   serving both (blocks of outputs x partners of about
+ *                   sqrt(tbuf_mb / pair size) orbitals each; acc_workgroups
+ *                   is then unused)
  * Defaults: acc_workgroups 2048, tbuf_mb 4096 (or $FOCK_TBUF_MB), fused_split
- * chosen to fill the compute units evenly. */
+ * chosen to fill the compute units evenly, pair symmetry on (off with
+ * $FOCK_NO_PAIR_SYMMETRY=1). */
 typedef struct {
   int32_t acc_workgroups;
   int32_t tbuf_mb;
   int32_t fused_split;
   int32_t no_fused;
+  int32_t no_pair_symmetry;
 } fock_tuning;
 
 /* fock_plan with explicit schedule knobs (tuning may be NULL = defaults). */

@@ -23,6 +23,10 @@ struct PairRef {
 //           same partner list) times partners (k', m) stored as int2 at
 //           part_off; every output block is covered by consecutive batches,
 //           the first of which writes its outputs (the rest add).
+//           mirror: the pairs are unordered (outputs and partners are two
+//           disjoint orbital blocks); a second accumulate pass gives the
+//           partners their share, conj(W_ab) = W_ba (first_mirror: it writes
+//           them rather than adds), and the pair energies count twice.
 //   energy: an explicit PairRef list at pair_off; its partial sum goes to slot.
 struct Batch {
   int32_t inst = 0;
@@ -30,6 +34,8 @@ struct Batch {
   size_t part_off = 0;  // bytes into the workspace
   int32_t nP = 0;
   int32_t first = 0;
+  int32_t mirror = 0;
+  int32_t first_mirror = 0;
   size_t pair_off = 0;  // bytes into the workspace
   int32_t npairs = 0;   // pairs in the batch (apply: nO*nP)
   int32_t slot = 0;
@@ -176,8 +182,8 @@ hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi
                                   const double* gscale, double hscale, bool backward, bool energy);
 // the instance's apply batches take its energy (the three-pass paths)
 bool batch_apply_energy(const Plan& p, int inst);
-// ebsum[slot] = fixed-order sum of the first n energy partials (epart)
-hipError_t launch_sum_slot(const Plan& p, long long n, int slot);
+// ebsum[slot] = mult * fixed-order sum of the first n energy partials (epart)
+hipError_t launch_sum_slot(const Plan& p, long long n, int slot, double mult);
 // E_x of a three-pass instance from its apply-with-energy slots
 hipError_t launch_aslot_finish(const Plan& p, int inst, double* ex);
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ);

@@ -276,12 +276,13 @@ __global__ __launch_bounds__(kBlock) void k_energy_batch(const PairRef* __restri
   if (threadIdx.x == 0) ebsum[slot] = tot;
 }
 
-// slots[slot] = sum of part[0..n) in a fixed order: Neumaier per thread over
-// a strided share, then the waves in order (1024 threads: the partials of a
-// batch run to tens of thousands, read once)
+// slots[slot] = mult * (sum of part[0..n)) in a fixed order: Neumaier per
+// thread over a strided share, then the waves in order (1024 threads: the
+// partials of a batch run to tens of thousands, read once).  mult is 2 for a
+// batch of unordered pairs (each stands for both orders), else 1.
 constexpr int kSumBlock = 1024;
 __global__ __launch_bounds__(kSumBlock) void k_sum_slot(const double* __restrict__ part, long long n,
-                                                        double* __restrict__ slots, int slot) {
+                                                        double* __restrict__ slots, int slot, double mult) {
   __shared__ double red[kSumBlock / 64];
   double sum = 0.0, comp = 0.0;
   for (long long i = threadIdx.x; i < n; i += kSumBlock) {
@@ -298,7 +299,7 @@ __global__ __launch_bounds__(kSumBlock) void k_sum_slot(const double* __restrict
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < kSumBlock / 64; ++w) t += red[w];
-    slots[slot] = t;
+    slots[slot] = mult * t;
   }
 }
 
@@ -366,7 +367,7 @@ hipError_t apply_batch_t(const Plan& p, const Batch& b, const void* psi, const d
                        b.nP, parts, qmap, tbuf, vtab, tw, occ, kw, static_cast<double*>(nullptr));
   p.prof.end(FOCK_K_PENCIL, p.stream);
   if (energy) {
-    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * g.n2, b.eslot);
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * g.n2, b.eslot, 1.0);
     if (e != hipSuccess) return e;
   }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
@@ -501,10 +502,10 @@ hipError_t launch_energy_reduce(const Plan& p, const Batch& b, const double* occ
 
 bool batch_apply_energy(const Plan& p, int inst) { return !p.inst[inst].fused; }
 
-hipError_t launch_sum_slot(const Plan& p, long long n, int slot) {
+hipError_t launch_sum_slot(const Plan& p, long long n, int slot, double mult) {
   p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
   hipLaunchKernelGGL(k_sum_slot, dim3(1), dim3(kSumBlock), 0, p.stream, reinterpret_cast<const double*>(p.ws + p.epart_off),
-                     n, reinterpret_cast<double*>(p.ws + p.ebsum_off), slot);
+                     n, reinterpret_cast<double*>(p.ws + p.ebsum_off), slot, mult);
   p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
   return hipGetLastError();
 }

@@ -337,9 +337,33 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_en
 // ---------------------------------------------------------------------------
 // accumulate pass: per (output, plane group), every partner of the batch
 // ---------------------------------------------------------------------------
-template <typename T, int L>
+// Batch pairs are pi = o nP + p (output o0 + o, partner parts[p]).
+//   MIRROR false: blockIdx.y = o; W of pair (o, p) for every p, times u_p.
+//   MIRROR true:  blockIdx.y = p, the partner is the output; for every o the
+//                 pair's W_{o p} gives W_{p o} = conj(W_{o p}), times u_{o0+o}.
+// The global band index of the orbital that multiplies W, and the pair slot.
+template <bool MIRROR>
+__device__ __forceinline__ void acc_source(int j, int blk, int o0, int nP, int nbands, const int2* __restrict__ parts,
+                                           int* band, size_t* pair) {
+  if (MIRROR) {
+    *band = o0 + j;
+    *pair = static_cast<size_t>(j) * nP + blk;
+  } else {
+    const int2 r = parts[j];
+    *band = r.x * nbands + r.y;
+    *pair = static_cast<size_t>(blk) * nP + j;
+  }
+}
+
+// u W (or u conj(W) for the mirror pass)
+template <bool MIRROR, typename C>
+__device__ __forceinline__ C acc_term(C u, C w) {
+  return MIRROR ? cmulconj(w, u) : cmul(u, w);
+}
+
+template <typename T, int L, bool MIRROR = false>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) void k_acc_reg(
-    int n1, int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
+    int n1, int nbands, long long bs, int o0, int nO, int nP, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
     const double* __restrict__ gscale, double hscale, int backward) {
@@ -354,15 +378,18 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   const int j1 = blockIdx.x * Sh::PL + pl;
   const bool valid = j1 < n1;
   const int o = blockIdx.y;
+  const int nsrc = MIRROR ? nO : nP;
   sp += pl * L * Sh::LP;
   C acc[L];
 #pragma unroll
   for (int j2 = 0; j2 < L; ++j2) acc[j2] = C{T(0), T(0)};
-  for (int p = 0; p < nP; ++p) {
-    const int2 r = parts[p];
+  for (int p = 0; p < nsrc; ++p) {
+    int sb;
+    size_t pair;
+    acc_source<MIRROR>(p, o, o0, nP, nbands, parts, &sb, &pair);
     C x[L];
     if (valid) {
-      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * n1 + static_cast<size_t>(j1) * LL + col;
+      const C* src = tbuf + pair * LL * n1 + static_cast<size_t>(j1) * LL + col;
 #pragma unroll
       for (int c3 = 0; c3 < L; ++c3) x[c3] = src[c3 * L];  // row (j1, c2 = col)
     } else {
@@ -373,8 +400,8 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
     transpose_plane<C, T, L>(x, sp, col);   // column (j1, j3 = col)
     reg_fft<C, L, +1>(x);                   // inverse axis 2: x[j2]
     if (valid) {
-      const T coef = static_cast<T>(-kw[r.x] * occ[r.x * nbands + r.y]);
-      const C* um = psi + static_cast<size_t>(r.x * nbands + r.y) * bs + static_cast<size_t>(j1) * LL + col;
+      const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
+      const C* um = psi + static_cast<size_t>(sb) * bs + static_cast<size_t>(j1) * LL + col;
       C mb[2][B];
 #pragma unroll
       for (int j = 0; j < B; ++j) mb[0][j] = um[j * L];
@@ -387,7 +414,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
         reg_fence();
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-          const C w = cmul(mb[n & 1][j], x[n * B + j]);
+          const C w = acc_term<MIRROR>(mb[n & 1][j], x[n * B + j]);
           acc[n * B + j].x += coef * w.x;
           acc[n * B + j].y += coef * w.y;
         }
@@ -395,7 +422,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
     }
   }
   if (!valid) return;  // no barrier after this point
-  const int okn = o0 + o;
+  const int okn = MIRROR ? parts[o].x * nbands + parts[o].y : o0 + o;
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[okn / nbands] * occ[okn];
@@ -633,9 +660,9 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_en
   if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-template <typename T, int L>
+template <typename T, int L, bool MIRROR = false>
 __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC)) void k_acc_split(
-    int n1, int nbands, long long bs, int o0, int nP, const int2* __restrict__ parts,
+    int n1, int nbands, long long bs, int o0, int nO, int nP, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
     const double* __restrict__ gscale, double hscale, int backward) {
@@ -652,15 +679,17 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
   // element (j1, 2m + h, col) of a grid: the lane's samples along axis 2
   const size_t eo = static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * L + col;
+  const int nsrc = MIRROR ? nO : nP;
   C acc[LH];
 #pragma unroll
   for (int m = 0; m < LH; ++m) acc[m] = C{T(0), T(0)};
-  for (int p = 0; p < nP; ++p) {
-    const int2 r = parts[p];
+  for (int p = 0; p < nsrc; ++p) {
+    int sb;
+    size_t pair;
+    acc_source<MIRROR>(p, o, o0, nP, nbands, parts, &sb, &pair);
     C y[LH];
     if (valid) {
-      const C* src = tbuf + (static_cast<size_t>(o) * nP + p) * LL * n1 + static_cast<size_t>(j1) * LL +
-                     static_cast<size_t>(h) * LH * L + col;
+      const C* src = tbuf + pair * LL * n1 + static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * LH * L + col;
 #pragma unroll
       for (int k = 0; k < LH; ++k) y[k] = src[k * L];  // row (j1, c2 = col), c3 = h L/2 + k
     } else {
@@ -671,8 +700,8 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
     transpose_split<C, T, L, true>(y, sp, col, h);  // column j3 = col, c2 = h L/2 + k
     split_fft_inv<C, L>(y, h);                      // inverse axis 2: y[m] at j2 = 2m + h
     if (valid) {
-      const T coef = static_cast<T>(-kw[r.x] * occ[r.x * nbands + r.y]);
-      const C* um = psi + static_cast<size_t>(r.x * nbands + r.y) * bs + eo;
+      const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
+      const C* um = psi + static_cast<size_t>(sb) * bs + eo;
       C mb[2][B];
 #pragma unroll
       for (int j = 0; j < B; ++j) mb[0][j] = um[j * 2 * L];
@@ -685,7 +714,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
         reg_fence();
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-          const C w = cmul(mb[n & 1][j], y[n * B + j]);
+          const C w = acc_term<MIRROR>(mb[n & 1][j], y[n * B + j]);
           acc[n * B + j].x += coef * w.x;
           acc[n * B + j].y += coef * w.y;
         }
@@ -693,7 +722,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
     }
   }
   if (!valid) return;  // no barrier after this point
-  const int okn = o0 + o;
+  const int okn = MIRROR ? parts[o].x * nbands + parts[o].y : o0 + o;
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[okn / nbands] * occ[okn];
@@ -864,30 +893,42 @@ int launch_pencil_energy(const Plan& p, const Batch& b, const Instance& in, cons
   }
 }
 
-template <typename T, int L>
+// mirror: the batch's partners are the outputs (see k_acc_reg)
+template <typename T, int L, bool MIRROR = false>
 void launch_acc(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
                 const void* psi, const double* occ, const double* kw, void* out, const double* gscale, double hscale,
                 bool backward) {
   using C = typename cx<T>::t;
   const int n1 = in.grid[0];
   const long long bs = static_cast<long long>(in.band_stride);
+  const int nout = MIRROR ? b.nP : b.nO;
+  const int first = MIRROR ? b.first_mirror : b.first;
   if constexpr (RegPolicy<T, L>::SPLIT_ACC) {
     using Sh = SplitShape<T, L>;
-    hipLaunchKernelGGL((k_acc_split<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.nO), dim3(Sh::NTP), Sh::LDS, p.stream,
-                       n1, in.nbands, bs, b.o0, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
-                       static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
+    hipLaunchKernelGGL((k_acc_split<T, L, MIRROR>), dim3((n1 + Sh::PL - 1) / Sh::PL, nout), dim3(Sh::NTP), Sh::LDS,
+                       p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
+                       static_cast<C*>(out), first, gscale, hscale, backward ? 1 : 0);
   } else {
     using Sh = RegShape<T, L>;
-    hipLaunchKernelGGL((k_acc_reg<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.nO), dim3(Sh::NTP), Sh::LDS, p.stream,
-                       n1, in.nbands, bs, b.o0, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
-                       static_cast<C*>(out), b.first, gscale, hscale, backward ? 1 : 0);
+    hipLaunchKernelGGL((k_acc_reg<T, L, MIRROR>), dim3((n1 + Sh::PL - 1) / Sh::PL, nout), dim3(Sh::NTP), Sh::LDS,
+                       p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
+                       static_cast<C*>(out), first, gscale, hscale, backward ? 1 : 0);
   }
+}
+
+// the accumulate pass of a batch, and its mirror pass for unordered pairs
+template <typename T, int L>
+void launch_acc_all(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
+                    const void* psi, const double* occ, const double* kw, void* out, const double* gscale,
+                    double hscale, bool backward) {
+  launch_acc<T, L, false>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale, backward);
+  if (b.mirror) launch_acc<T, L, true>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale, backward);
 }
 
 template <typename T, int L>
 void reg_lds_attr(int lim) {
   using Po = RegPolicy<T, L>;
-  const void* fs[3];
+  const void* fs[4];
   if constexpr (Po::SPLIT_PLANE) {
     fs[0] = reinterpret_cast<const void*>(&k_plane_split<T, L, false>);
     fs[1] = reinterpret_cast<const void*>(&k_plane_split<T, L, true>);
@@ -895,10 +936,13 @@ void reg_lds_attr(int lim) {
     fs[0] = reinterpret_cast<const void*>(&k_plane_reg<T, L, false>);
     fs[1] = reinterpret_cast<const void*>(&k_plane_reg<T, L, true>);
   }
-  if constexpr (Po::SPLIT_ACC)
-    fs[2] = reinterpret_cast<const void*>(&k_acc_split<T, L>);
-  else
-    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L>);
+  if constexpr (Po::SPLIT_ACC) {
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<T, L, false>);
+    fs[3] = reinterpret_cast<const void*>(&k_acc_split<T, L, true>);
+  } else {
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L, false>);
+    fs[3] = reinterpret_cast<const void*>(&k_acc_reg<T, L, true>);
+  }
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
@@ -930,12 +974,15 @@ int launch_pencil_mixed(const Plan& p, const Batch& b, const Instance& in, const
 template <int L>
 void mixed_lds_attr(int lim) {
   using Acc = RegPolicy<double, L>;
-  const void* fs[3] = {reinterpret_cast<const void*>(&k_plane_reg<float, L, false, double>),
-                       reinterpret_cast<const void*>(&k_plane_reg<float, L, true, double>), nullptr};
-  if constexpr (Acc::SPLIT_ACC)
-    fs[2] = reinterpret_cast<const void*>(&k_acc_split<double, L>);
-  else
-    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L>);
+  const void* fs[4] = {reinterpret_cast<const void*>(&k_plane_reg<float, L, false, double>),
+                       reinterpret_cast<const void*>(&k_plane_reg<float, L, true, double>), nullptr, nullptr};
+  if constexpr (Acc::SPLIT_ACC) {
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<double, L, false>);
+    fs[3] = reinterpret_cast<const void*>(&k_acc_split<double, L, true>);
+  } else {
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L, false>);
+    fs[3] = reinterpret_cast<const void*>(&k_acc_reg<double, L, true>);
+  }
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
@@ -984,12 +1031,12 @@ hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const dou
   p.prof.end(FOCK_K_PENCIL, p.stream);
   if (!ok) return hipErrorInvalidValue;
   if (energy) {
-    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot);
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot, b.mirror ? 2.0 : 1.0);
     if (e != hipSuccess) return e;
   }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
-  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale,
-                                                        backward)));
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc_all<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale,
+                                                            backward)));
   p.prof.end(FOCK_K_ACCUMULATE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1038,12 +1085,12 @@ hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const d
   p.prof.end(FOCK_K_PENCIL, p.stream);
   if (!ok) return hipErrorInvalidValue;
   if (energy) {
-    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot);
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot, b.mirror ? 2.0 : 1.0);
     if (e != hipSuccess) return e;
   }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
-  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc<double, N>(p, b, in, parts, t64, psi, occ, kw, out, gscale, hscale,
-                                                             backward)));
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc_all<double, N>(p, b, in, parts, t64, psi, occ, kw, out, gscale,
+                                                                 hscale, backward)));
   p.prof.end(FOCK_K_ACCUMULATE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();

@@ -102,6 +102,16 @@ void build_kernel_table(const Instance& in, const double q[3], std::vector<doubl
       }
 }
 
+// every k' is a partner of every k, in order (the full k-pair set)
+bool full_kset(const Instance& in) {
+  for (int k = 0; k < in.nk; ++k) {
+    if (static_cast<int>(in.kpartners[k].size()) != in.nk) return false;
+    for (int kp = 0; kp < in.nk; ++kp)
+      if (in.kpartners[k][kp] != kp) return false;
+  }
+  return true;
+}
+
 size_t env_mb(const char* name, size_t dflt) {
   const char* s = std::getenv(name);
   if (!s || !*s) return dflt;
@@ -147,7 +157,7 @@ fock_status validate_desc(const fock_desc& d, int idx) {
 
 fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, const fock_tuning* tune,
                        Plan** out) {
-  const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0};
+  const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0, 0};
   auto p = std::make_unique<Plan>();
   p->prec = prec;
   p->csize = prec == FOCK_C64 ? 8 : 16;
@@ -215,6 +225,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const bool no_fused = tn.no_fused != 0 || (nofused && *nofused && *nofused != '0');
   const char* noreg = std::getenv("FOCK_NO_REG");
   const bool no_reg = noreg && *noreg && *noreg != '0';
+  const char* nosym = std::getenv("FOCK_NO_PAIR_SYMMETRY");
+  const bool no_sym = tn.no_pair_symmetry != 0 || (nosym && *nosym && *nosym != '0');
   for (auto& in : p->inst) {
     in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
@@ -300,6 +312,43 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     }
     const size_t pair_bytes = static_cast<size_t>(in.npts) * p->csize;
     const int pmax = static_cast<int>(std::max<size_t>(1, std::min<size_t>(65535, tbuf_target / pair_bytes)));
+    if (in.reg && !no_sym && g.k0 == 0 && g.k1 == in.nk && full_kset(in)) {
+      // Pair symmetry: W_ba = conj(W_ab) (the Nyquist-averaged kernel is even
+      // in c -> -c, q -> -q), so each unordered pair is transformed once.  The
+      // orbitals (partner order = global order k' nbands + m) are cut into
+      // blocks of bs; block pair (I, J), I < J, is one batch whose accumulate
+      // pass serves I and whose mirror pass serves J; the pairs inside a block
+      // run as an ordinary batch.  Batches run in sequence on one stream, so
+      // no output is written by two launches at once.
+      int bs = std::max(1, std::min(nout, static_cast<int>(std::sqrt(static_cast<double>(pmax)))));
+      const int nblk = (nout + bs - 1) / bs;
+      bs = (nout + nblk - 1) / nblk;
+      std::vector<char> touched(nblk, 0);
+      for (int I = 0; I < nblk; ++I) {
+        const int i0 = I * bs, ni = std::min(bs, nout - i0);
+        for (int J = I; J < nblk; ++J) {
+          const int j0 = J * bs, nj = std::min(bs, nout - j0);
+          Batch b;
+          b.inst = g.inst;
+          b.o0 = i0;
+          b.nO = ni;
+          b.part_off = g.off + static_cast<size_t>(j0) * 2 * sizeof(int32_t);
+          b.nP = nj;
+          b.first = touched[I] ? 0 : 1;
+          touched[I] = 1;
+          if (J != I) {
+            b.mirror = 1;
+            b.first_mirror = touched[J] ? 0 : 1;
+            touched[J] = 1;
+          }
+          b.npairs = ni * nj;
+          max_pairs_elems = std::max(max_pairs_elems, static_cast<size_t>(b.npairs) * in.npts);
+          p->apply_batches.push_back(b);
+          p->apply_fft_pairs += b.npairs;
+        }
+      }
+      continue;
+    }
     int nO = std::max(1, std::min(nout, (acc_wgs + in.grid[0] - 1) / in.grid[0]));
     nO = std::min(nO, pmax);
     const int nP = std::max(1, std::min(npart, pmax / nO));
@@ -428,7 +477,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
                                  : std::max(plane, tile) * p->csize + 64;
     p->lds_needed = std::max(p->lds_needed, need);
   }
-  p->apply_launches = 3 * static_cast<int64_t>(p->apply_batches.size());
+  p->apply_launches = 0;
+  for (const Batch& b : p->apply_batches) p->apply_launches += b.mirror ? 4 : 3;
   for (const FusedGroup& g : p->fused_groups) p->apply_launches += g.nsplit > 1 ? 2 : 1;
 
   // ---- host image of the constant prefix ----

@@ -28,7 +28,7 @@ def test_apply_model_per_pair(L, flops_m, bytes_mb32):
 
 
 def test_roofline_picks_dominant_kernel_and_bound():
-    stats = {"apply_fft_pairs": 1_000_000, "energy_fft_pairs": 500_000}
+    stats = {"ordered_pairs": 1_000_000, "apply_fft_pairs": 1_000_000, "energy_fft_pairs": 500_000}
     kern = {"fused": (200.0, 2), "energy_fused": (20.0, 1), "overlap": (1.0, 1)}
     r = bench.roofline(kern, stats, (32, 32, 32), 8, 78.6)
     assert r["kernel"] == "fused" and r["launches"] == 2
@@ -47,7 +47,7 @@ def test_three_pass_apply_is_rated_as_one_unit():
     """The three passes of a batch are one apply: 4 s N per ordered pair over
     their summed time, never a per-pass byte figure (which caches can push
     above the peak)."""
-    stats = {"apply_fft_pairs": 1_638_400, "energy_fft_pairs": 0}
+    stats = {"ordered_pairs": 1_638_400, "apply_fft_pairs": 1_638_400, "energy_fft_pairs": 0}
     kern = {"plane": (2 * 2650.0, 2 * 1215), "pencil": (2 * 2040.0, 2 * 1215), "accumulate": (2 * 2350.0, 2 * 1215),
             "overlap": (17.0, 1)}
     r = bench.roofline(kern, stats, (72, 72, 72), 8, 78.6)
@@ -62,8 +62,26 @@ def test_three_pass_apply_is_rated_as_one_unit():
     assert rates["three_pass"]["gbs"] == pytest.approx(gbs, rel=1e-3)
 
 
+def test_symmetric_three_pass_apply_is_rated_per_ordered_pair():
+    """With pair symmetry the plane and pencil passes transform each unordered
+    pair once, the accumulate and mirror passes serve every ordered pair; the
+    apply is still rated by 4 s N per ordered pair."""
+    ordered, fft = 1_638_400, 842_715
+    stats = {"ordered_pairs": ordered, "apply_fft_pairs": fft, "energy_fft_pairs": 0}
+    kern = {"plane": (2 * 1100.0, 2 * 630), "pencil": (2 * 900.0, 2 * 630), "accumulate": (2 * 2300.0, 2 * 1225)}
+    r = bench.roofline(kern, stats, (72, 72, 72), 8, 78.6)
+    assert r["kernel"] == bench.THREE_PASS_UNIT and r["launches"] == 2 * 630
+    per_launch_s = (1100.0 + 900.0 + 2300.0) / 630 * 1e-3
+    gbs = 4 * 8 * 72 ** 3 * (ordered / 630) / per_launch_s / 1e9
+    assert r["alt"]["hbm_gbs"] == pytest.approx(gbs, rel=1e-3)
+    rates = bench.kernel_rates(kern, stats, (72, 72, 72), 8)
+    m = bench.kernel_model((72, 72, 72), 8)
+    assert rates["plane"]["tflops"] == pytest.approx(m["plane"]["flops"] * 2 * fft / 2.2 / 1e12, rel=1e-2)
+    assert rates["accumulate"]["tflops"] == pytest.approx(m["accumulate"]["flops"] * 2 * ordered / 4.6 / 1e12, rel=1e-2)
+
+
 def test_whole_pair_kernel_dominates_when_larger():
-    stats = {"apply_fft_pairs": 1000, "energy_fft_pairs": 0}
+    stats = {"ordered_pairs": 1000, "apply_fft_pairs": 1000, "energy_fft_pairs": 0}
     kern = {"fused": (100.0, 2), "plane": (10.0, 4), "pencil": (10.0, 4), "accumulate": (10.0, 4)}
     assert bench.dominant_apply(kern)[0] == "fused"
     kern["plane"] = (90.0, 4)

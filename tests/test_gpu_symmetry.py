@@ -1,0 +1,129 @@
+"""Pair symmetry of the three-pass register-line path against the oracle.
+
+With the full k-pair set the planner cuts the orbitals into blocks and
+transforms each unordered pair once: the accumulate pass serves the block of
+outputs, the mirror pass the block of partners with conj(W), and the pair
+energies count twice.  A small pair-buffer budget (tuning tbuf_mb) forces
+several blocks on small grids, including blocks of one orbital and a ragged
+last block.  Each case checks fock_apply (with overlaps), fock_apply_energy,
+fock_energy and fock_energy_backward against the oracle to the parity
+tolerances, and against the same plan built without pair symmetry.
+Non-uniform k weights and fractional occupations make the two sides of every
+pair carry different factors.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.fock_oracle import Oracle
+from paper_1111_0716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": dict(e=1e-12, v=1e-12), "c64": dict(e=1e-6, v=1e-5), "mixed": dict(e=1e-6, v=1e-5)}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def band_err(got, ref):
+    got = got.reshape(ref.shape)
+    err = 0.0
+    for k in range(ref.shape[0]):
+        for n in range(ref.shape[1]):
+            err = max(err, np.linalg.norm(got[k, n] - ref[k, n]) / np.linalg.norm(ref[k, n]))
+    return err
+
+
+# grid, k-mesh, bands, precision, tbuf_mb; comments: pairs per block budget -> blocks
+CASES = [
+    ((32, 24, 24), (2, 1, 1), 3, "c64", 1),    # 7 pairs -> blocks of 2 (3 blocks)
+    ((32, 24, 24), (1, 1, 1), 7, "c64", 1),    # blocks 2, 2, 2, 1 (ragged)
+    ((24, 32, 32), (2, 1, 1), 3, "c128", 1),   # 2 pairs -> blocks of one orbital
+    ((24, 32, 32), (1, 2, 1), 4, "c128", 3),   # 7 pairs -> blocks 2, 2, 2, 2
+    ((24, 60, 60), (2, 1, 1), 2, "c64", 2),    # two-lane accumulate (FP32 54-64)
+    ((24, 40, 40), (2, 1, 1), 2, "c128", 2),   # two-lane accumulate (FP64 >= 36)
+    ((24, 32, 32), (2, 1, 1), 3, "mixed", 1),  # FP64 accumulate of the mixed path
+    ((72, 24, 24), (1, 1, 2), 3, "c64", 2),    # pencil of length 72 (two-lane), 3 planes per group
+]
+
+
+def _plans(inst, prec, tbuf, device):
+    from paper_1111_0716_amd import fock
+
+    sym = fock.Plan([inst], precision=prec, device=device, tuning={"tbuf_mb": tbuf})
+    ref = fock.Plan([inst], precision=prec, device=device, tuning={"tbuf_mb": tbuf, "no_pair_symmetry": 1})
+    return sym, ref
+
+
+@pytest.mark.parametrize("grid,kmesh,nb,prec,tbuf", CASES)
+def test_pair_symmetric_batches_match_oracle(grid, kmesh, nb, prec, tbuf, device):
+    import torch
+
+    log(f"symmetry case grid={grid} kmesh={kmesh} nb={nb} prec={prec} tbuf_mb={tbuf}")
+    inst = inputs.small_instance(grid=grid, kmesh=kmesh, nbands=nb, seed=(310, sum(grid) + nb))
+    nk = inst.nk
+    rng = np.random.default_rng([310, nk, nb])
+    w = rng.uniform(0.5, 1.5, size=nk)
+    inst.kweight = w / w.sum()
+    dt = np.complex64 if prec == "c64" else np.complex128
+    psi_np = np.ascontiguousarray(inst.psi.astype(dt))
+    sym, ref = _plans(inst, prec, tbuf, device)
+    st_s, st_r = sym.stats(), ref.stats()
+    log(f"  fft pairs {st_s['apply_fft_pairs']} (symmetric) vs {st_r['apply_fft_pairs']}, "
+        f"launches {st_s['apply_launches']} vs {st_r['apply_launches']}")
+    assert st_s["apply_fft_pairs"] < st_r["apply_fft_pairs"], "the case does not reach the symmetric schedule"
+    psi = torch.from_numpy(psi_np).to(device)
+    occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
+    (vx,), (vm,) = sym.fock_apply([psi], [occ], vmat=True)
+    (vx2,), _, ex2 = sym.fock_apply_energy([psi], [occ])
+    ex = sym.fock_energy([psi], [occ])
+    gex = torch.full((1,), 0.75, dtype=torch.float64, device=device)
+    o = Oracle.from_instance(inst)
+    (gg,) = sym.fock_energy_backward([psi], [occ], gex, 2.0 * o.dv)
+    (vr,), _ = ref.fock_apply([psi], [occ])
+    torch.cuda.synchronize()
+    assert torch.equal(vx, vx2), "fock_apply_energy's V_x psi differs from fock_apply's"
+    vref, eref = o.apply(psi_np.astype(np.complex128), inst.occ)
+    gref = o.gradient(psi_np.astype(np.complex128), inst.occ, vref)
+    mref = o.overlap(psi_np.astype(np.complex128), vref)
+    tol = TOL[prec]
+    ev = band_err(vx.cpu().numpy(), vref)
+    e1 = abs(float(ex2.item()) - eref) / abs(eref)
+    e2 = abs(float(ex.item()) - eref) / abs(eref)
+    eg = band_err(gg.cpu().numpy(), 0.75 * gref)
+    em = np.max(np.abs(vm.cpu().numpy() - mref)) / np.max(np.abs(mref))
+    es = band_err(vx.cpu().numpy(), vr.cpu().numpy().reshape(vref.shape))
+    log(f"  V_x {ev:.2e}  E_x(apply) {e1:.2e}  E_x(energy) {e2:.2e}  grad {eg:.2e}  M {em:.2e}  "
+        f"vs ordered {es:.2e}")
+    assert ev <= tol["v"] and eg <= tol["v"] and em <= tol["v"]
+    assert e1 <= tol["e"] and e2 <= tol["e"]
+    assert es <= 2 * tol["v"]
+    sym.close()
+    ref.close()
+
+
+def test_symmetric_schedule_is_deterministic(device):
+    """FP64 results of the symmetric schedule are bitwise reproducible from
+    call to call and under graph replay."""
+    import torch
+
+    from paper_1111_0716_amd import fock
+
+    inst = inputs.small_instance(grid=(24, 32, 32), kmesh=(2, 1, 1), nbands=3, seed=(311, 0))
+    stream = torch.cuda.Stream(device=device)
+    plan = fock.Plan([inst], precision="c128", device=device, tuning={"tbuf_mb": 1}, stream=stream)
+    psi = torch.from_numpy(inst.psi).to(device)
+    occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
+    outs = []
+    for graph in (False, True, True):
+        plan.set_graph(graph)
+        with torch.cuda.stream(stream):
+            (v,), _, e = plan.fock_apply_energy([psi], [occ])
+        stream.synchronize()
+        outs.append((v.clone(), e.clone()))
+    for v, e in outs[1:]:
+        assert torch.equal(v, outs[0][0]) and torch.equal(e, outs[0][1])
+    plan.close()
