@@ -59,7 +59,12 @@ typedef enum {
   FOCK_ERR_UNSUPPORTED = 2, /* valid but not supported (grid axis not {2,3,5}-smooth or > 72)     */
   FOCK_ERR_NOMEM = 3,       /* host allocation failed, or workspace smaller than required          */
   FOCK_ERR_DEVICE = 4,      /* no usable GPU, or a HIP call / kernel launch failed                */
-  FOCK_ERR_STATE = 5        /* call out of order (e.g. apply before fock_set_workspace)           */
+  FOCK_ERR_STATE = 5,       /* call out of order (e.g. apply before fock_set_workspace)           */
+  /* not statuses: they make the type span int32, so any int32 a caller passes
+   * where an enum of this header is expected is a value the library may read
+   * (and reject) */
+  FOCK_STATUS_RANGE_MIN_ = -2147483647 - 1,
+  FOCK_STATUS_RANGE_MAX_ = 2147483647
 } fock_status;
 
 /* FOCK_C128: complex128 throughout.  FOCK_C64: complex64 orbitals, FP32
@@ -68,7 +73,13 @@ typedef enum {
  * multiply, inverse transforms and accumulate in FP64 (the paper's "some of
  * the FFTs in single precision"); grids N1 x L x L with N1 and L each 24,
  * 32, 36, 40, 48, 50, 54, 60, 64 or 72 only (FOCK_ERR_UNSUPPORTED otherwise). */
-typedef enum { FOCK_C128 = 0, FOCK_C64 = 1, FOCK_MIXED = 2 } fock_precision;
+typedef enum {
+  FOCK_C128 = 0,
+  FOCK_C64 = 1,
+  FOCK_MIXED = 2,
+  FOCK_PRECISION_RANGE_MIN_ = -2147483647 - 1, /* not precisions (see fock_status) */
+  FOCK_PRECISION_RANGE_MAX_ = 2147483647
+} fock_precision;
 
 /* One exchange problem ("instance").  All pointers are HOST pointers and are
  * only read during fock_plan. */

@@ -59,5 +59,75 @@ def build(verbose=True):
     return LIB
 
 
+# ---- host-code sanitizer build ------------------------------------------
+# A variant for checking the host code (planner, C ABI, launch set-up) on
+# the CPU: host code built with AddressSanitizer and UndefinedBehaviorSanitizer
+# (-Xarch_host: the device code is compiled as usual, at -O1), into
+# _build/sanitize/.  Load it by setting FOCK_LIBRARY to its path with the ASan
+# runtime preloaded (asan_runtime()).
+SAN_DIR = os.path.join(BUILD, "sanitize")
+SAN_LIB = os.path.join(SAN_DIR, "libfock_host_sanitized.so")
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime():
+    """Path of the compiler's shared ASan runtime (to preload)."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError(f"ASan runtime not found ({path!r})")
+    return path
+
+
+def _sources_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)) + ["../../include/fock.h"]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    with open(os.path.abspath(__file__), "rb") as f:  # the commands themselves
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def build_host_sanitized(verbose=False):
+    """Build (or reuse, when the sources are unchanged) the sanitizer variant."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    stamp = os.path.join(SAN_DIR, "sources.sha256")
+    digest = _sources_digest()
+    if os.path.exists(SAN_LIB) and os.path.exists(stamp) and open(stamp).read() == digest:
+        return SAN_LIB
+
+    def one(src):
+        obj = os.path.join(SAN_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-O1", "-Xarch_host", "-g", "-std=c++17", "-fPIC",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Wno-unused-command-line-argument", *SAN_FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitizer compile of {src} failed:\n{' '.join(cmd)}\n{r.stderr}")
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    tmp = SAN_LIB + ".tmp"
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *SAN_FLAGS, *objs, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitizer link failed:\n{' '.join(cmd)}\n{r.stderr}")
+    os.replace(tmp, SAN_LIB)
+    with open(stamp, "w") as f:
+        f.write(digest)
+    if verbose:
+        print(f"built {SAN_LIB}", file=sys.stderr)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
-    build()
+    if sys.argv[1:] == ["sanitize"]:
+        build_host_sanitized(verbose=True)
+    else:
+        build()

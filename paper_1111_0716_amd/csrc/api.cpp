@@ -545,6 +545,7 @@ const char* fock_status_string(fock_status s) {
     case FOCK_ERR_NOMEM: return "FOCK_ERR_NOMEM: out of memory or workspace too small";
     case FOCK_ERR_DEVICE: return "FOCK_ERR_DEVICE: GPU unavailable or HIP error";
     case FOCK_ERR_STATE: return "FOCK_ERR_STATE: call out of order";
+    default: break;
   }
   return "unknown fock_status";
 }

@@ -538,7 +538,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     std::memcpy(img + in.kw_off, in.kweight.data(), in.kweight.size() * sizeof(double));
     tables[i].clear();
   }
-  for (const Group& g : groups) std::memcpy(img + g.off, g.parts.data(), g.parts.size() * sizeof(int32_t));
+  for (const Group& g : groups)
+    if (!g.parts.empty()) std::memcpy(img + g.off, g.parts.data(), g.parts.size() * sizeof(int32_t));
   for (int i = 0; i < n_inst; ++i) {
     const Instance& in = p->inst[i];
     if (in.n_ebatches == 0) continue;

@@ -15,7 +15,9 @@ from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_size_
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfock.so")
+# FOCK_LIBRARY selects another build of the library (the host-code sanitizer
+# variant of build.build_host_sanitized); default: the in-tree libfock.so
+LIB_PATH = os.environ.get("FOCK_LIBRARY") or os.path.join(HERE, "libfock.so")
 
 FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FOCK_ERR_STATE = range(6)
 FOCK_C128, FOCK_C64, FOCK_MIXED = 0, 1, 2

@@ -1,0 +1,85 @@
+"""Seeded fuzz of the host side of the C ABI (no GPU): random descriptors,
+precisions and schedule knobs through fock_plan_tuned, then the workspace
+size, the plan counters and fock_destroy.  Every call must return a status
+(FOCK_OK, FOCK_ERR_ARG or FOCK_ERR_UNSUPPORTED) with a message for errors,
+and accepted plans must count N_k-pair lists x N_b^2 ordered pairs, run no
+more band-pair transforms than that, and ask for a workspace.  The same test
+runs under AddressSanitizer and UndefinedBehaviorSanitizer in
+test_host_sanitizers.py."""
+import ctypes
+
+import numpy as np
+
+from paper_1111_0716_amd import fock, inputs
+
+
+def _random_case(rng):
+    keep = []
+    kind = rng.integers(0, 6)
+    if kind == 0:
+        lat = rng.normal(size=(3, 3)) * 8.0
+    elif kind == 1:
+        lat = inputs.rhombohedral_lattice(float(rng.uniform(5, 20)), float(rng.uniform(40, 100)))
+    elif kind == 2:
+        lat = np.zeros((3, 3))  # singular
+        lat[0, 0] = 1.0
+    else:
+        lat = inputs.cubic_lattice(float(rng.uniform(3, 20)))
+    if rng.uniform() < 0.05:
+        lat = lat.copy()
+        lat[1, 1] = np.nan
+    choices = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 14, 16, 24, 25, 27, 32, 36, 40, 72, 80]
+    grid = [int(rng.choice(choices)) for _ in range(3)]
+    if int(np.prod(grid)) > 40000:  # keep the host kernel tables small
+        grid = [min(g, 16) for g in grid]
+    nk = int(rng.integers(0, 5)) if rng.uniform() < 0.1 else int(rng.integers(1, 5))
+    kfrac = rng.uniform(-0.5, 0.5, size=(max(nk, 1), 3))
+    kweight = None
+    if rng.uniform() < 0.3:
+        kweight = rng.uniform(-0.1, 1.0, size=max(nk, 1))
+    kpairs = None
+    if rng.uniform() < 0.4 and nk >= 1:
+        npairs = int(rng.integers(1, nk * nk + 1))
+        kpairs = rng.integers(-1 if rng.uniform() < 0.1 else 0, nk + (1 if rng.uniform() < 0.1 else 0),
+                              size=(npairs, 2))
+    nbands = int(rng.integers(-1, 6))
+    n = int(np.prod(grid))
+    band_stride = n + int(rng.integers(-2, 40)) if rng.uniform() < 0.5 else None
+    mu = float(rng.choice([0.106, 0.3, 0.0, -1.0, np.inf])) if rng.uniform() < 0.2 else 0.106
+    d = fock.make_desc(lat, grid, kfrac, kweight if kweight is None or len(kweight) == kfrac.shape[0] else None,
+                       max(nbands, 0), band_stride, mu, kpairs, keep)
+    d.nk = nk
+    d.nbands = nbands
+    prec = int(rng.choice([0, 1, 2, 3, -1, 7]))
+    tn = None
+    if rng.uniform() < 0.5:
+        tn = fock.FockTuning(acc_workgroups=int(rng.integers(-1, 4000)), tbuf_mb=int(rng.integers(-1, 64)),
+                             fused_split=int(rng.integers(-1, 6)), no_fused=int(rng.integers(0, 2)),
+                             no_pair_symmetry=int(rng.integers(0, 2)))
+    return d, keep, prec, tn, kpairs, nk, nbands
+
+
+def test_descriptor_fuzz():
+    L = fock.lib()
+    rng = np.random.default_rng(20261203)
+    seen = {fock.FOCK_OK: 0, fock.FOCK_ERR_ARG: 0, fock.FOCK_ERR_UNSUPPORTED: 0}
+    for it in range(400):
+        d, keep, prec, tn, kpairs, nk, nbands = _random_case(rng)
+        h = ctypes.c_void_p()
+        st = L.fock_plan_tuned((fock.FockDesc * 1)(d), 1, prec, None, ctypes.byref(tn) if tn is not None else None,
+                               ctypes.byref(h))
+        assert st in seen, (it, st)
+        seen[st] += 1
+        if st != fock.FOCK_OK:
+            assert L.fock_last_error().decode(), it
+            assert not h.value, it
+            continue
+        size = ctypes.c_size_t()
+        assert L.fock_workspace_size(h, ctypes.byref(size)) == fock.FOCK_OK and size.value > 0
+        a, b, c, e = (ctypes.c_int64() for _ in range(4))
+        assert L.fock_plan_stats(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(e)) == fock.FOCK_OK
+        npair_lists = nk * nk if kpairs is None else len(kpairs)
+        assert a.value == npair_lists * nbands * nbands, it
+        assert 0 <= b.value <= a.value and 0 <= c.value <= a.value, it
+        assert L.fock_destroy(h) == fock.FOCK_OK
+    assert all(v > 0 for v in seen.values()), seen
