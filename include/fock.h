@@ -175,6 +175,25 @@ fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* 
 fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const double* const* occ,
                               void* const* vx_psi, void* const* vmat, double* ex);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fock_apply_energy with the plan's workspace taken from a library-owned
+ * device array of FOCK_STATIC_WORKSPACE_BYTES bytes instead of one attached
+ * with fock_set_workspace (which need not have been called).  The array is a
+ * static __device__ object, one per device, held until the process ends; the
+ * call runs on the current device and allocates nothing (no hipMalloc, no
+ * events, no graphs: launches are always eager).  It uploads the plan's
+ * tables into the array with hipMemcpyAsync on the plan stream unless the
+ * previous call on this device was made with the same plan.
+ * Outputs as fock_apply_energy (vx_psi, vmat and ex bitwise equal to its).
+ * Errors: FOCK_ERR_NOMEM, before any other check, when fock_workspace_size
+ * exceeds FOCK_STATIC_WORKSPACE_BYTES; otherwise as fock_apply_energy.
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (other threads or streams) race and give wrong results. */
+#define FOCK_STATIC_WORKSPACE_BYTES (64u << 20)
+fock_status fock_apply_energy_static(fock_plan_t plan, const void* const* psi, const double* const* occ,
+                                     void* const* vx_psi, void* const* vmat, double* ex);
+
 /* Gradient of E_x: grad_psi[i] (psi layout, device) receives
  *   grad_ex[i] * scale * w_k * f_{k,n} * (V_x u)_{k,n}
  * with grad_ex a device FP64 array [n_inst] and scale a host number; the

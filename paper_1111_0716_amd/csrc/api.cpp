@@ -3,6 +3,7 @@
 #include <cstdint>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -155,6 +156,62 @@ fock_status run_energy(Plan* p, const void* const* psi, const double* const* occ
                                                   : launch_energy_finish(*p, ii, ex + i);
     if (e != hipSuccess) return hip_fail(e, "energy finish launch");
   }
+  return FOCK_OK;
+}
+
+// Argument checks of the apply-with-energy calls (after check_ready).
+fock_status check_apply_energy_args(const Plan* p, const void* const* psi, const double* const* occ,
+                                    void* const* vx_psi, const double* ex) {
+  fock_status s;
+  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
+  if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
+  for (size_t i = 0; i < p->inst.size(); ++i)
+    if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
+  return FOCK_OK;
+}
+
+// The launches of fock_apply_energy on the plan's current workspace.
+fock_status run_apply_energy(Plan* p, const void* const* psi, const double* const* occ, void* const* vx_psi,
+                             void* const* vmat, double* ex) {
+  fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false, true);
+  if (st != FOCK_OK) return st;
+  if ((st = run_overlaps(p, psi, vx_psi, vmat)) != FOCK_OK) return st;
+  return run_energy(p, psi, occ, ex, true);
+}
+
+// ---- library-owned workspace of fock_apply_energy_static -----------------
+// One array per device, kept until the process ends.  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kStaticWorkspaceBytes = static_cast<size_t>(FOCK_STATIC_WORKSPACE_BYTES);
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+constexpr int kMaxDevices = 64;
+struct StaticSlot {
+  unsigned char* ptr = nullptr;  // device address of `scratch` on this device
+  uint64_t owner = 0;            // serial of the plan whose tables it holds (0: none)
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kMaxDevices];
+
+// The current device's array (its address looked up on first use) and its
+// slot; FOCK_ERR_DEVICE if the device or the lookup fails.
+fock_status static_workspace(StaticSlot** slot) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return set_error(FOCK_ERR_DEVICE, "device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& s = g_static[dev];
+  if (!s.ptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "static workspace lookup");
+    s.ptr = static_cast<unsigned char*>(ptr);
+  }
+  *slot = &s;
   return FOCK_OK;
 }
 
@@ -369,23 +426,59 @@ fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const do
   Plan* p = reinterpret_cast<Plan*>(plan);
   fock_status s = check_ready(p);
   if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
-  if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
-  auto enqueue = [&]() -> fock_status {
-    fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false, true);
-    if (st != FOCK_OK) return st;
-    if ((st = run_overlaps(p, psi, vx_psi, vmat)) != FOCK_OK) return st;
-    return run_energy(p, psi, occ, ex, true);
-  };
+  if ((s = check_apply_energy_args(p, psi, occ, vx_psi, ex)) != FOCK_OK) return s;
+  auto enqueue = [&]() -> fock_status { return run_apply_energy(p, psi, occ, vx_psi, vmat, ex); };
   return with_graph(p, p->g_apply_energy,
                     ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
                                 reinterpret_cast<const void* const*>(vmat)},
                             {reinterpret_cast<uintptr_t>(vmat), reinterpret_cast<uintptr_t>(ex)}),
                     enqueue);
+}
+
+fock_status fock_apply_energy_static(fock_plan_t plan, const void* const* psi, const double* const* occ,
+                                     void* const* vx_psi, void* const* vmat, double* ex) {
+  clear_error();
+  Plan* p = reinterpret_cast<Plan*>(plan);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  if (p->total_bytes > kStaticWorkspaceBytes)
+    return set_error(FOCK_ERR_NOMEM, "plan needs " + std::to_string(p->total_bytes) +
+                                         " bytes of workspace; the static workspace holds " +
+                                         std::to_string(kStaticWorkspaceBytes));
+  fock_status s = check_apply_energy_args(p, psi, occ, vx_psi, ex);
+  if (s != FOCK_OK) return s;
+  if ((s = device_ok()) != FOCK_OK) return s;
+  size_t max_lds = 0;
+  hipError_t e = prepare_kernels(p->prec, &max_lds);
+  if (e != hipSuccess) return hip_fail(e, "device query");
+  if (p->lds_needed > max_lds)
+    return set_error(FOCK_ERR_UNSUPPORTED, "grid needs " + std::to_string(p->lds_needed) +
+                                               " bytes of LDS per workgroup; the device allows " +
+                                               std::to_string(max_lds));
+  StaticSlot* slot = nullptr;
+  if ((s = static_workspace(&slot)) != FOCK_OK) return s;
+  // tables into the array unless this plan's are still there (the last call on
+  // this device was this plan's)
+  if (slot->owner != p->serial) {
+    e = hipMemcpyAsync(slot->ptr, p->host_image.data(), p->const_bytes, hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) {
+      slot->owner = 0;
+      return hip_fail(e, "table upload");
+    }
+    slot->owner = p->serial;
+  }
+  // run eagerly on the array, without event timing (events would be created);
+  // the plan's own workspace is restored afterwards
+  unsigned char* const ws = p->ws;
+  const size_t ws_bytes = p->ws_bytes;
+  const bool prof_on = p->prof.on;
+  p->ws = slot->ptr;
+  p->ws_bytes = kStaticWorkspaceBytes;
+  p->prof.on = false;
+  s = run_apply_energy(p, psi, occ, vx_psi, vmat, ex);
+  p->ws = ws;
+  p->ws_bytes = ws_bytes;
+  p->prof.on = prof_on;
+  return s;
 }
 
 fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const double* const* occ,

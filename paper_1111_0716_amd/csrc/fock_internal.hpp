@@ -101,6 +101,7 @@ struct GraphCache {
 };
 
 struct Plan {
+  uint64_t serial = 0;  // distinct for every plan of the process (never reused)
   fock_precision prec;
   size_t csize;  // sizeof(complex element) of orbitals and outputs
   // orbitals, outputs and overlaps are complex128 (FOCK_C128 and FOCK_MIXED)

@@ -3,6 +3,7 @@
 // Host work only; nothing here touches the device.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <memory>
 #include <cstdlib>
@@ -158,7 +159,9 @@ fock_status validate_desc(const fock_desc& d, int idx) {
 fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, const fock_tuning* tune,
                        Plan** out) {
   const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0, 0};
+  static std::atomic<uint64_t> next_serial{1};
   auto p = std::make_unique<Plan>();
+  p->serial = next_serial.fetch_add(1);
   p->prec = prec;
   p->csize = prec == FOCK_C64 ? 8 : 16;
   const size_t rsize = prec == FOCK_C64 ? 4 : 8;  // kernel tables: FP64 unless the whole path is FP32

@@ -22,9 +22,10 @@ LIB_PATH = os.environ.get("FOCK_LIBRARY") or os.path.join(HERE, "libfock.so")
 FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FOCK_ERR_STATE = range(6)
 FOCK_C128, FOCK_C64, FOCK_MIXED = 0, 1, 2
 PRECISIONS = {"c128": FOCK_C128, "c64": FOCK_C64, "mixed": FOCK_MIXED}
+STATIC_WORKSPACE_BYTES = 64 << 20  # FOCK_STATIC_WORKSPACE_BYTES of fock.h
 
 EXPORTED = ["fock_plan", "fock_plan_tuned", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",
-            "fock_apply_energy", "fock_energy", "fock_energy_backward", "fock_pw_to_grid", "fock_grid_to_pw", "fock_apply_pw", "fock_dft3",
+            "fock_apply_energy", "fock_apply_energy_static", "fock_energy", "fock_energy_backward", "fock_pw_to_grid", "fock_grid_to_pw", "fock_apply_pw", "fock_dft3",
             "fock_plan_stats", "fock_profile_enable", "fock_profile_read", "fock_set_graph", "fock_destroy",
             "fock_status_string", "fock_last_error"]
 KERNEL_KINDS = ["plane", "pencil", "accumulate", "energy_plane", "energy_pencil", "energy_reduce", "overlap",
@@ -86,6 +87,8 @@ def lib():
         L.fock_energy.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]
         L.fock_apply_energy.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
                                         POINTER(c_void_p), c_void_p]
+        L.fock_apply_energy_static.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
+                                               POINTER(c_void_p), c_void_p]
         L.fock_energy_backward.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_double,
                                            POINTER(c_void_p)]
         L.fock_pw_to_grid.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(c_void_p),
@@ -164,13 +167,15 @@ class Plan:
     (e.g. paper_1111_0716_amd.inputs.Instance) or dicts with those keys.
     ``band_stride``: per instance, elements between bands (default N): grid
     tensors are then [nk, nbands, band_stride] with the grid in the first N.
+    ``attach_workspace``: False leaves the plan without a workspace (only
+    fock_apply_energy_static, which brings its own, can then run).
     ``precision``: "c64" (FP32 path), "c128" (FP64 path) or "mixed" (complex128
     orbitals and outputs, FP32 co-densities and forward transforms, FP64 kernel
     multiply, inverse transforms and accumulate; grids N1 x L x L, N1 and L in
     24, 32, 36, 40, 48, 50, 54, 60, 64, 72)."""
 
     def __init__(self, instances, precision="c64", device=None, stream=None, kpairs=None, tuning=None,
-                 band_stride=None):
+                 band_stride=None, attach_workspace=True):
         import torch
 
         self.torch = torch
@@ -209,7 +214,8 @@ class Plan:
         check(lib().fock_workspace_size(self.handle, ctypes.byref(size)))
         self.workspace_bytes = size.value
         self.workspace = None
-        self.set_workspace(torch.empty(max(size.value, 256), dtype=torch.uint8, device=self.device))
+        if attach_workspace:
+            self.set_workspace(torch.empty(max(size.value, 256), dtype=torch.uint8, device=self.device))
 
     def set_workspace(self, buf):
         """Attach a device buffer of at least ``workspace_bytes`` bytes (uint8,
@@ -310,6 +316,32 @@ class Plan:
                                       _ptrs([o.data_ptr() for o in occ]), _ptrs([x.data_ptr() for x in out]),
                                       _ptrs([x.data_ptr() for x in mats]) if mats else None, c_void_p(ex.data_ptr())))
         return out, mats, ex
+
+    def fock_apply_energy_static(self, psi, occ, out=None, vmat=None, ex=None):
+        """fock_apply_energy on the library's static device workspace (the
+        library allocates nothing; outputs are the caller's tensors, or new
+        ones made here when not given).  ``vmat``: None, or a list of overlap
+        tensors [nk, nbands, nbands].  Returns (outputs, vmat, E_x)."""
+        psi, occ = self._inputs(psi, occ)
+        out = self._outputs(out, psi)
+        if vmat is not None:
+            vmat = _aslist(vmat)
+            self._check_count("vmat", vmat)
+            for i, (x, m) in enumerate(zip(vmat, self.meta)):
+                if not (x.is_cuda and x.dtype == self.cdtype and x.is_contiguous() and x.device == self.device and
+                        tuple(x.shape) == (m["nk"], m["nbands"], m["nbands"])):
+                    raise ValueError(f"vmat[{i}] must be a contiguous {self.cdtype} tensor "
+                                     f"({m['nk']}, {m['nbands']}, {m['nbands']}) on {self.device}")
+        if ex is None:
+            ex = self.torch.empty(len(psi), dtype=self.torch.float64, device=self.device)
+        self._check_ex(ex)
+        self._sync_stream()
+        with self.torch.cuda.device(self.device):
+            check(lib().fock_apply_energy_static(self.handle, _ptrs([p.data_ptr() for p in psi]),
+                                                 _ptrs([o.data_ptr() for o in occ]), _ptrs([x.data_ptr() for x in out]),
+                                                 _ptrs([x.data_ptr() for x in vmat]) if vmat else None,
+                                                 c_void_p(ex.data_ptr())))
+        return out, vmat, ex
 
     def fock_energy(self, psi, occ, ex=None):
         """E_x of every instance as a float64 tensor [n_inst]."""

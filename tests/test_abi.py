@@ -167,3 +167,33 @@ def test_mixed_precision_plans_need_register_line_grids():
     arr = (fock.FockDesc * 1)(d)
     h = ctypes.c_void_p()
     assert L.fock_plan(arr, 1, 3, None, ctypes.byref(h)) == fock.FOCK_ERR_ARG
+
+
+def test_static_workspace_limit_and_checks():
+    """fock_apply_energy_static: the size limit of fock.h, FOCK_ERR_NOMEM for a
+    plan whose workspace exceeds it (before anything else), argument errors
+    on the host, and no GPU -> FOCK_ERR_DEVICE."""
+    m = re.search(r"#define\s+FOCK_STATIC_WORKSPACE_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == fock.STATIC_WORKSPACE_BYTES
+    L = fock.lib()
+    keep = []
+    one, two = fock._ptrs([1]), fock._ptrs([2])
+    big = fock.make_desc(inputs.cubic_lattice(10.0), (32, 32, 32), inputs.gamma_mesh(4, 4, 1), nbands=4, keep=keep)
+    h = ctypes.c_void_p()
+    assert L.fock_plan((fock.FockDesc * 1)(big), 1, fock.FOCK_C128, None, ctypes.byref(h)) == fock.FOCK_OK
+    size = ctypes.c_size_t()
+    L.fock_workspace_size(h, ctypes.byref(size))
+    assert size.value > fock.STATIC_WORKSPACE_BYTES
+    assert L.fock_apply_energy_static(h, one, one, two, None, ctypes.c_void_p(1)) == fock.FOCK_ERR_NOMEM
+    assert str(fock.STATIC_WORKSPACE_BYTES) in L.fock_last_error().decode()
+    L.fock_destroy(h)
+    small = fock.make_desc(inputs.cubic_lattice(10.0), (8, 8, 8), np.zeros((1, 3)), nbands=2, keep=keep)
+    assert L.fock_plan((fock.FockDesc * 1)(small), 1, fock.FOCK_C64, None, ctypes.byref(h)) == fock.FOCK_OK
+    assert L.fock_apply_energy_static(None, one, one, two, None, ctypes.c_void_p(1)) == fock.FOCK_ERR_ARG
+    assert L.fock_apply_energy_static(h, one, one, two, None, None) == fock.FOCK_ERR_ARG
+    assert L.fock_apply_energy_static(h, one, one, one, None, ctypes.c_void_p(1)) == fock.FOCK_ERR_ARG
+    assert L.fock_apply_energy_static(h, None, one, two, None, ctypes.c_void_p(1)) == fock.FOCK_ERR_ARG
+    import torch
+    if not torch.cuda.is_available():
+        assert L.fock_apply_energy_static(h, one, one, two, None, ctypes.c_void_p(1)) == fock.FOCK_ERR_DEVICE
+    L.fock_destroy(h)
