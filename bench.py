@@ -152,16 +152,24 @@ def roofline(kern, stats, grid, s, peak_tflops, traffic=None):
     return roof
 
 
-def unit_traffic(workload, dom):
+def unit_traffic(workload, dom, kern=None):
     """Counter bytes per launch of the dominant unit from the committed
-    traffic summaries (the three passes summed), or None."""
+    traffic summaries, or None.  The three-pass unit is one batch: its plane
+    and pencil dispatch plus its accumulate dispatches (two for a batch of
+    unordered pairs: the mirror pass), each kind's bytes per dispatch times
+    its dispatches per batch in the step (`kern`)."""
     pattern = TRAFFIC_FILES.get(workload)
     if not pattern:
         return None
     from paper_1111_0716_amd.profile_summary import read_traffic
     kinds = THREE_PASS if dom == THREE_PASS_UNIT else (dom,)
     vals = [read_traffic(os.path.join(ROOT, pattern.format(kind=k)), k) for k in kinds]
-    return None if any(v is None for v in vals) else sum(vals)
+    if any(v is None for v in vals):
+        return None
+    if dom == THREE_PASS_UNIT and kern:
+        batches = kern["plane"][1]
+        return sum(v * kern[k][1] / batches for k, v in zip(kinds, vals))
+    return sum(vals)
 
 
 def kernel_rates(kern, stats, grid, s):
@@ -186,6 +194,18 @@ def kernel_rates(kern, stats, grid, s):
                              "gbs": round(model["fused"]["bytes"] * units["fused"] / sec / 1e9, 1),
                              "tflops": round(model["fused"]["flops"] * units["fused"] / sec / 1e12, 3)}
     return out
+
+
+def launch_gaps(r):
+    """Device time per step outside the library's kernels: the step time
+    (events around each step on the stream) minus the summed per-launch
+    event spans, with the launches per step."""
+    kern = r["kernels"]
+    busy = sum(v[0] for v in kern.values())
+    n = sum(v[1] for v in kern.values())
+    idle = r["ms_per_step"] - busy
+    return {"launches_per_step": n, "kernel_ms_per_step": round(busy, 3), "idle_ms_per_step": round(idle, 3),
+            "idle_frac": round(idle / r["ms_per_step"], 4), "idle_us_per_launch": round(1e3 * idle / max(n, 1), 2)}
 
 
 def copy_bandwidth(device, mib=1024, reps=5):
@@ -660,7 +680,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--beta-steps", type=int, default=3,
                     help="timed steps of the beta-boron 72^3 leg of the default run (0: skip it)")
-    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw", "precision"], default="alpha")
+    ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw", "precision", "membw"],
+                    default="alpha")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (the reference dispatch "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -678,6 +699,8 @@ def main():
         return pw(args)
     if args.workload == "precision":
         return precision(args)
+    if args.workload == "membw":
+        return membw(args)
 
     import torch
 
@@ -719,7 +742,7 @@ def main():
     value = pairs / (r32["ms_per_step"] / 1e3)
     dom = dominant_apply(r32["kernels"])[0]
     roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
-                    traffic=unit_traffic(args.workload, dom))
+                    traffic=unit_traffic(args.workload, dom, r32["kernels"]))
     copy_gbs = copy_bandwidth(device)
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["hbm_frac_vs_copy"] = round(roof["alt"]["hbm_gbs"] / copy_gbs, 4)
@@ -741,6 +764,7 @@ def main():
                    "ordered_pairs_per_step": pairs, "grid": list(inst.grid), "nk": inst.nk, "nbands": inst.nbands},
         "roofline": roof,
         "ms_per_step_median": round(r32["ms_median"], 3),
+        "launch_gaps": launch_gaps(r32),
         "fp32": {"ms_per_step": round(r32["ms_per_step"], 3), "pairs_per_s": round(value, 1),
                  "kernels_ms": {k: round(v[0], 3) for k, v in r32["kernels"].items() if v[1]},
                  "kernel_rates": kernel_rates(r32["kernels"], r32["stats"], inst.grid, 8),
@@ -763,6 +787,41 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def membw(args):
+    """Device memory bandwidth against working-set size: a full read (sum of
+    a float32 buffer) and a copy (half the set read, half written), each
+    repeated; sets that fit the 256 MB Infinity Cache are served from it on
+    repeats, larger ones stream from HBM.  One JSON line per size."""
+    import torch
+
+    device = torch.device("cuda:0")
+    buf = torch.zeros(2048 << 18, dtype=torch.float32, device=device)  # 2 GiB
+    dst = torch.empty(1024 << 18, dtype=torch.float32, device=device)
+    out = []
+    for mib in (32, 64, 128, 192, 256, 384, 512, 1024, 2048):
+        n = mib << 18  # float32 elements
+        reps = 50 if mib <= 256 else 10
+        x, h = buf[:n], n // 2
+        for kind in ("read", "copy"):
+            def op():
+                if kind == "read":
+                    return x.sum()
+                return dst[:h].copy_(x[:h])
+            op()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                op()
+            e1.record()
+            torch.cuda.synchronize()
+            gbs = (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+            out.append({"working_set_mib": mib, "kind": kind, "gbs": round(gbs, 1)})
+            log(f"  {mib:5d} MiB {kind}: {gbs:8.1f} GB/s")
+    print(json.dumps({"metric": "device memory bandwidth vs working set", "unit": "GB/s (bytes read + written)",
+                      "results": out, "host": host_info()}), flush=True)
+
+
 def beta_leg(args, device):
     """The largest workload (beta-boron-shaped 72^3, 2x2x2 k-mesh, 160 bands)
     on the FP32 path, timed like the headline: fock_apply_energy + backward
@@ -777,10 +836,12 @@ def beta_leg(args, device):
     log(f"  {r['ms_per_step']:.1f} ms/step")
     pairs = r["stats"]["ordered_pairs"]
     dom = dominant_apply(r["kernels"])[0]
-    roof = roofline(r["kernels"], r["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"], traffic=unit_traffic("beta", dom))
+    roof = roofline(r["kernels"], r["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
+                    traffic=unit_traffic("beta", dom, r["kernels"]))
     return {"workload": WORKLOADS["3"], "ordered_pairs_per_step": pairs, "steps": args.beta_steps, "warmup": w,
             "ms_per_step": round(r["ms_per_step"], 3), "pairs_per_s": round(pairs / (r["ms_per_step"] / 1e3), 1),
-            "roofline": roof, "kernels_ms": {k: round(v[0], 3) for k, v in r["kernels"].items() if v[1]},
+            "roofline": roof, "launch_gaps": launch_gaps(r),
+            "kernels_ms": {k: round(v[0], 3) for k, v in r["kernels"].items() if v[1]},
             "kernel_rates": kernel_rates(r["kernels"], r["stats"], inst.grid, 8)}
 
 

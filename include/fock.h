@@ -119,15 +119,20 @@ fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision pre
  *                   serving both (blocks of outputs x partners of about
  *                   sqrt(tbuf_mb / pair size) orbitals each; acc_workgroups
  *                   is then unused)
+ *   fused_rounds    1: whole-pair path on 32^3 FP32 grids by unordered pairs
+ *                   (one workgroup per pair, rounds of pairwise disjoint
+ *                   pairs, one launch per round; needs a k-pair list closed
+ *                   under swapping); 0: one workgroup per output
  * Defaults: acc_workgroups 2048, tbuf_mb 4096 (or $FOCK_TBUF_MB), fused_split
  * chosen to fill the compute units evenly, pair symmetry on (off with
- * $FOCK_NO_PAIR_SYMMETRY=1). */
+ * $FOCK_NO_PAIR_SYMMETRY=1), fused_rounds off (on with $FOCK_FUSED_ROUNDS=1). */
 typedef struct {
   int32_t acc_workgroups;
   int32_t tbuf_mb;
   int32_t fused_split;
   int32_t no_fused;
   int32_t no_pair_symmetry;
+  int32_t fused_rounds;
 } fock_tuning;
 
 /* fock_plan with explicit schedule knobs (tuning may be NULL = defaults). */
@@ -293,6 +298,18 @@ fock_status fock_profile_read(fock_plan_t plan, int kind, double* total_ms, int6
  * records a new graph).  Needs a plan stream other than the legacy default
  * stream (FOCK_ERR_STATE otherwise).  Results are identical to eager launches. */
 fock_status fock_set_graph(fock_plan_t plan, int enable);
+
+/* Call records.  When the environment variable FOCK_LOG names a file (or is
+ * "stderr") at fock_plan, the plan records every call of fock_apply,
+ * fock_apply_energy, fock_energy, fock_energy_backward, fock_pw_to_grid,
+ * fock_grid_to_pw, fock_apply_pw and fock_dft3 (not fock_apply_energy_static,
+ * which creates nothing): one JSON line per call with the status, the host
+ * enqueue time, the device time between events recorded on the plan stream
+ * around the call (device_ms -1 where no workspace was attached), and the
+ * plan's counters; at fock_destroy, one summary line per call name (calls,
+ * device time, ordered pairs per second).  Lines are written at fock_destroy,
+ * or when 1024 records are pending (the host then waits for their events).
+ * Records add two events per call to the stream and nothing else. */
 
 /* Release the plan (host memory; the caller frees the workspace). NULL is a no-op. */
 fock_status fock_destroy(fock_plan_t plan);

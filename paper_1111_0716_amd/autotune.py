@@ -1,15 +1,20 @@
 """Autotuner for the schedule knobs of libfock (fock_tuning).
 
-It times one fock_apply per candidate on the device with the library's own
-per-kernel events and keeps the fastest, searching one knob at a time:
+It times one fock_apply per candidate schedule on the device with the
+library's own per-kernel events and keeps the fastest.  Candidates, for the
+paths the plan uses (read from the kernels a default apply launches):
 
-  whole-pair path   fused_split in {1, 2, 3, 4}       (partner slices per output)
-  three-pass path   acc_workgroups in {512 .. 8192}    (output block size)
-                    tbuf_mb in {1024, 4096, 16384}     (pairs per batch)
+  whole-pair path   one workgroup per output with fused_split in {1, 2, 3, 4}
+                    partner slices, and unordered-pair rounds (fused_rounds)
+  three-pass path   pair symmetry with the pair-buffer budget tbuf_mb in
+                    {128 .. 16384} MiB (which sets the block size; 128 and
+                    256 MiB keep a batch's pair buffer within the 256 MB
+                    Infinity Cache), and the ordered schedule over the joint
+                    grid tbuf_mb x acc_workgroups (output block size)
 
-Only knobs of the paths the plan actually uses are searched (read from the
-kernels a default apply launches).  Results are cached as JSON keyed by the
-device name, precision and the instance shapes, in $FOCK_TUNE_CACHE or
+Candidates whose plans come out identical (same counters and workspace on
+the host) are timed once.  Results are cached as JSON keyed by the device
+name, precision and the instance shapes, in $FOCK_TUNE_CACHE or
 ~/.cache/fock_tune.json.
 """
 from __future__ import annotations
@@ -21,10 +26,49 @@ import numpy as np
 
 from . import fock
 
-KNOBS = ("acc_workgroups", "tbuf_mb", "fused_split", "no_fused")
+KNOBS = ("acc_workgroups", "tbuf_mb", "fused_split", "no_fused", "no_pair_symmetry", "fused_rounds")
 FUSED_SPLITS = (1, 2, 3, 4)
-ACC_WORKGROUPS = (512, 1024, 2048, 4096, 8192)
-TBUF_MB = (1024, 4096, 16384)
+SYM_TBUF_MB = (128, 256, 512, 1024, 4096, 16384)
+ORDERED_TBUF_MB = (256, 1024, 4096, 16384)
+ORDERED_ACC_WORKGROUPS = (512, 2048, 8192)
+
+
+def candidates(kinds):
+    """Candidate knob sets for the kernel kinds a default apply launched."""
+    out = [{}]
+    if "fused" in kinds:
+        out += [{"fused_split": sp} for sp in FUSED_SPLITS] + [{"fused_rounds": 1}]
+    if kinds & {"plane", "pencil", "accumulate"}:
+        out += [{"tbuf_mb": tb} for tb in SYM_TBUF_MB]
+        out += [{"no_pair_symmetry": 1, "tbuf_mb": tb, "acc_workgroups": aw}
+                for tb in ORDERED_TBUF_MB for aw in ORDERED_ACC_WORKGROUPS]
+    return out
+
+
+def plan_signature(instances, precision, tuning):
+    """Counters and workspace size of the plan these knobs give (host only):
+    equal signatures mean the same schedule."""
+    import ctypes
+
+    keep = []
+    descs = (fock.FockDesc * len(instances))()
+    for i, inst in enumerate(instances):
+        descs[i] = fock.make_desc(fock._get(inst, "lattice"), fock._get(inst, "grid"), fock._get(inst, "kfrac"),
+                                  fock._get(inst, "kweight", None), fock._get(inst, "nbands"), None,
+                                  fock._get(inst, "mu", 0.106), fock._get(inst, "kpairs", None), keep)
+    L = fock.lib()
+    h = ctypes.c_void_p()
+    tn = fock.FockTuning(**{k: int(v) for k, v in tuning.items()})
+    fock.check(L.fock_plan_tuned(descs, len(instances), fock.PRECISIONS[precision], None, ctypes.byref(tn),
+                                 ctypes.byref(h)))
+    try:
+        size = ctypes.c_size_t()
+        a, b, c, e = (ctypes.c_int64() for _ in range(4))
+        fock.check(L.fock_workspace_size(h, ctypes.byref(size)))
+        fock.check(L.fock_plan_stats(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(e)))
+        return (a.value, b.value, e.value, size.value)
+    finally:
+        L.fock_destroy(h)
 
 
 def cache_path():
@@ -104,23 +148,15 @@ def autotune(instances, psi, occ, precision="c64", device=None, use_cache=True, 
 
     best = {}
     best_ms, kinds = run(best)
-    if "fused" in kinds:
-        for sp in FUSED_SPLITS:
-            t = dict(best, fused_split=sp)
-            ms, _ = run(t)
-            if ms < best_ms:
-                best_ms, best = ms, t
-    if kinds & {"plane", "pencil", "accumulate"}:
-        for aw in ACC_WORKGROUPS:
-            t = dict(best, acc_workgroups=aw)
-            ms, _ = run(t)
-            if ms < best_ms:
-                best_ms, best = ms, t
-        for tb in TBUF_MB:
-            t = dict(best, tbuf_mb=tb)
-            ms, _ = run(t)
-            if ms < best_ms:
-                best_ms, best = ms, t
+    seen = {plan_signature(instances, precision, best)}
+    for t in candidates(kinds)[1:]:
+        sig = plan_signature(instances, precision, t)
+        if sig in seen:
+            continue
+        seen.add(sig)
+        ms, _ = run(t)
+        if ms < best_ms:
+            best_ms, best = ms, t
     record = {"tuning": best, "ms": best_ms, "trials": trials}
     if use_cache:
         entries = load_cache()

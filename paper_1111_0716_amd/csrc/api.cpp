@@ -1,6 +1,8 @@
 // C ABI of libfock.so (declared in include/fock.h).
+#include <chrono>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <initializer_list>
 #include <mutex>
@@ -60,6 +62,114 @@ void Profiler::release() {
   for (auto& v : spans) v.clear();
 }
 
+// ---- call records (FOCK_LOG) ----------------------------------------------
+namespace {
+
+hipEvent_t log_event(CallLog& L) {
+  if (!L.pool.empty()) {
+    hipEvent_t e = L.pool.back();
+    L.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void log_open(Plan* p) {
+  const char* path = std::getenv("FOCK_LOG");
+  if (!path || !*path) return;
+  CallLog& L = p->log;
+  L.serial = p->serial;
+  if (std::strcmp(path, "stderr") == 0) {
+    L.f = stderr;
+  } else {
+    L.f = std::fopen(path, "a");
+    L.own = L.f != nullptr;
+  }
+}
+
+// Write the pending records (waiting for their events) and recycle the events.
+void log_flush(const Plan* p, CallLog& L) {
+  for (CallLog::Rec& r : L.pending) {
+    double ms = -1.0;
+    if (r.e0 && r.e1) {
+      float t = 0.0f;
+      if (hipEventSynchronize(r.e1) == hipSuccess && hipEventElapsedTime(&t, r.e0, r.e1) == hipSuccess) ms = t;
+      (void)hipGetLastError();
+    }
+    std::fprintf(L.f,
+                 "{\"plan\": %llu, \"call\": \"%s\", \"status\": %d, \"graph\": %d, \"enqueue_us\": %.1f, "
+                 "\"device_ms\": %.4f, \"instances\": %zu, \"ordered_pairs\": %lld, \"apply_fft_pairs\": %lld, "
+                 "\"apply_launches\": %lld}\n",
+                 static_cast<unsigned long long>(L.serial), r.call, r.status, r.graph ? 1 : 0, r.enqueue_us, ms,
+                 p->inst.size(), static_cast<long long>(p->ordered_pairs), static_cast<long long>(p->apply_fft_pairs),
+                 static_cast<long long>(p->apply_launches));
+    CallLog::Total* tot = nullptr;
+    for (auto& kv : L.totals)
+      if (kv.first == r.call) tot = &kv.second;
+    if (!tot) {
+      L.totals.emplace_back(r.call, CallLog::Total{});
+      tot = &L.totals.back().second;
+    }
+    tot->calls += 1;
+    if (ms > 0.0) tot->device_ms += ms;
+    if (r.e0) L.pool.push_back(r.e0);
+    if (r.e1) L.pool.push_back(r.e1);
+  }
+  L.pending.clear();
+  std::fflush(L.f);
+}
+
+// Run one API call's body `f`, recorded when the plan logs.
+template <typename F>
+fock_status logged(Plan* p, const char* name, F&& f) {
+  CallLog& L = p->log;
+  if (!L.on()) return f();
+  const auto t0 = std::chrono::steady_clock::now();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p->uploaded && (e0 = log_event(L)) != nullptr && hipEventRecord(e0, p->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    L.pool.push_back(e0);
+    e0 = nullptr;
+  }
+  const fock_status st = f();
+  if (e0 && (e1 = log_event(L)) != nullptr && hipEventRecord(e1, p->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    L.pool.push_back(e1);
+    e1 = nullptr;
+  }
+  const double us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+  L.pending.push_back(CallLog::Rec{name, static_cast<int>(st), us, p->use_graph, e0, e1});
+  if (L.pending.size() >= 1024) log_flush(p, L);
+  return st;
+}
+
+}  // namespace
+
+Plan::~Plan() {
+  if (log.on()) {
+    log_flush(this, log);
+    for (const auto& kv : log.totals)
+      std::fprintf(log.f,
+                   "{\"plan\": %llu, \"summary\": \"%s\", \"calls\": %lld, \"device_ms\": %.4f, "
+                   "\"ordered_pairs_per_s\": %.1f}\n",
+                   static_cast<unsigned long long>(log.serial), kv.first.c_str(),
+                   static_cast<long long>(kv.second.calls), kv.second.device_ms,
+                   kv.second.device_ms > 0.0 ? kv.second.calls * static_cast<double>(ordered_pairs) /
+                                                   (kv.second.device_ms * 1e-3)
+                                             : 0.0);
+    std::fflush(log.f);
+    for (hipEvent_t e : log.pool) (void)hipEventDestroy(e);
+    if (log.own) std::fclose(log.f);
+  }
+  prof.release();
+  release_graphs();
+}
+
 namespace {
 
 fock_status device_ok() {
@@ -112,6 +222,12 @@ fock_status run_apply(Plan* p, const void* const* psi, const double* const* occ,
                                             gscale ? gscale + g.inst : nullptr, hscale, backward,
                                             eblk ? eblk + g.eblk0 : nullptr);
     if (e != hipSuccess) return hip_fail(e, "whole-pair apply launch");
+  }
+  for (const FusedRounds& r : p->fused_rounds) {
+    const hipError_t e = launch_fused_rounds(*p, r, psi[r.inst], occ[r.inst], out[r.inst],
+                                             gscale ? gscale + r.inst : nullptr, hscale, backward,
+                                             eblk ? eblk + r.eblk0 : nullptr);
+    if (e != hipSuccess) return hip_fail(e, "whole-pair round launch");
   }
   for (const Batch& b : p->apply_batches) {
     const hipError_t e = launch_apply_batch(*p, b, psi[b.inst], occ[b.inst], out[b.inst], with_energy,
@@ -319,10 +435,11 @@ fock_status fock_plan_tuned(const fock_desc* descs, int32_t n_inst, fock_precisi
   try {
     Plan* p = nullptr;
     if (tuning && (tuning->acc_workgroups < 0 || tuning->tbuf_mb < 0 || tuning->fused_split < 0 ||
-                   tuning->fused_split > 4))
+                   tuning->fused_split > 4 || tuning->fused_rounds < 0 || tuning->fused_rounds > 1))
       return set_error(FOCK_ERR_ARG, "tuning knob out of range");
     const fock_status s = build_plan(descs, n_inst, prec, hip_stream, tuning, &p);
     if (s != FOCK_OK) return s;
+    log_open(p);
     *out = reinterpret_cast<fock_plan_t>(p);
     return FOCK_OK;
   } catch (const std::bad_alloc&) {
@@ -388,51 +505,60 @@ fock_status fock_apply(fock_plan_t plan, const void* const* psi, const double* c
                        void* const* vmat) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
-  auto enqueue = [&]() -> fock_status {
-    fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false);
-    if (st != FOCK_OK) return st;
-    return run_overlaps(p, psi, vx_psi, vmat);
-  };
-  return with_graph(p, p->g_apply,
-                    ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
-                                reinterpret_cast<const void* const*>(vmat)},
-                            {reinterpret_cast<uintptr_t>(vmat)}),
-                    enqueue);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_apply", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_psi), "vx_psi")) != FOCK_OK) return s;
+    for (size_t i = 0; i < p->inst.size(); ++i)
+      if (vx_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "vx_psi aliases psi");
+    auto enqueue = [&]() -> fock_status {
+      fock_status st = run_apply(p, psi, occ, vx_psi, nullptr, 1.0, false);
+      if (st != FOCK_OK) return st;
+      return run_overlaps(p, psi, vx_psi, vmat);
+    };
+    return with_graph(p, p->g_apply,
+                      ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
+                                  reinterpret_cast<const void* const*>(vmat)},
+                              {reinterpret_cast<uintptr_t>(vmat)}),
+                      enqueue);
+  });
 }
 
 fock_status fock_energy(fock_plan_t plan, const void* const* psi, const double* const* occ, double* ex) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
-  if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
-  return with_graph(p, p->g_energy, ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ)},
-                                            {reinterpret_cast<uintptr_t>(ex)}),
-                    [&]() { return run_energy(p, psi, occ, ex, false); });
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_energy", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+    if (!ex) return set_error(FOCK_ERR_ARG, "ex is NULL");
+    return with_graph(p, p->g_energy, ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ)},
+                                              {reinterpret_cast<uintptr_t>(ex)}),
+                      [&]() { return run_energy(p, psi, occ, ex, false); });
+  });
 }
 
 fock_status fock_apply_energy(fock_plan_t plan, const void* const* psi, const double* const* occ,
                               void* const* vx_psi, void* const* vmat, double* ex) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_apply_energy_args(p, psi, occ, vx_psi, ex)) != FOCK_OK) return s;
-  auto enqueue = [&]() -> fock_status { return run_apply_energy(p, psi, occ, vx_psi, vmat, ex); };
-  return with_graph(p, p->g_apply_energy,
-                    ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
-                                reinterpret_cast<const void* const*>(vmat)},
-                            {reinterpret_cast<uintptr_t>(vmat), reinterpret_cast<uintptr_t>(ex)}),
-                    enqueue);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_apply_energy", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_apply_energy_args(p, psi, occ, vx_psi, ex)) != FOCK_OK) return s;
+    auto enqueue = [&]() -> fock_status { return run_apply_energy(p, psi, occ, vx_psi, vmat, ex); };
+    return with_graph(p, p->g_apply_energy,
+                      ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(vx_psi),
+                                  reinterpret_cast<const void* const*>(vmat)},
+                              {reinterpret_cast<uintptr_t>(vmat), reinterpret_cast<uintptr_t>(ex)}),
+                      enqueue);
+  });
 }
 
 fock_status fock_apply_energy_static(fock_plan_t plan, const void* const* psi, const double* const* occ,
@@ -486,26 +612,28 @@ fock_status fock_energy_backward(fock_plan_t plan, const void* const* psi, const
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
   if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    if (!p->inst[i].symmetric)
-      return set_error(FOCK_ERR_UNSUPPORTED, "instance " + std::to_string(i) +
-                                                 ": the gradient needs a k-pair list closed under swapping (k, k') -> (k', k)");
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(grad_psi), "grad_psi")) != FOCK_OK) return s;
-  if (!grad_ex) return set_error(FOCK_ERR_ARG, "grad_ex is NULL");
-  if (!std::isfinite(scale)) return set_error(FOCK_ERR_ARG, "scale not finite");
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    if (grad_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "grad_psi aliases psi");
-  uint64_t sbits;
-  static_assert(sizeof(sbits) == sizeof(scale), "double is 64-bit");
-  std::memcpy(&sbits, &scale, sizeof(sbits));
-  return with_graph(p, p->g_backward,
-                    ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(grad_psi)},
-                            {reinterpret_cast<uintptr_t>(grad_ex), static_cast<uintptr_t>(sbits)}),
-                    [&]() { return run_apply(p, psi, occ, grad_psi, grad_ex, scale, true); });
+  return logged(p, "fock_energy_backward", [&]() -> fock_status {
+    for (size_t i = 0; i < p->inst.size(); ++i)
+      if (!p->inst[i].symmetric)
+        return set_error(FOCK_ERR_UNSUPPORTED, "instance " + std::to_string(i) +
+                                                   ": the gradient needs a k-pair list closed under swapping (k, k') -> (k', k)");
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_ptrs(p, psi, "psi")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(grad_psi), "grad_psi")) != FOCK_OK) return s;
+    if (!grad_ex) return set_error(FOCK_ERR_ARG, "grad_ex is NULL");
+    if (!std::isfinite(scale)) return set_error(FOCK_ERR_ARG, "scale not finite");
+    for (size_t i = 0; i < p->inst.size(); ++i)
+      if (grad_psi[i] == psi[i]) return set_error(FOCK_ERR_ARG, "grad_psi aliases psi");
+    uint64_t sbits;
+    static_assert(sizeof(sbits) == sizeof(scale), "double is 64-bit");
+    std::memcpy(&sbits, &scale, sizeof(sbits));
+    return with_graph(p, p->g_backward,
+                      ptr_key(p, {psi, reinterpret_cast<const void* const*>(occ), reinterpret_cast<const void* const*>(grad_psi)},
+                              {reinterpret_cast<uintptr_t>(grad_ex), static_cast<uintptr_t>(sbits)}),
+                      [&]() { return run_apply(p, psi, occ, grad_psi, grad_ex, scale, true); });
+  });
 }
 
 fock_status fock_set_graph(fock_plan_t plan, int enable) {
@@ -525,24 +653,30 @@ fock_status fock_pw_to_grid(fock_plan_t plan, const void* const* coef, const int
                             const int32_t* const* npw, const int32_t* npw_max, void* const* psi) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, coef, "coef")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(psi), "psi")) != FOCK_OK) return s;
-  if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
-  return run_pw_to_grid(p, coef, gidx, npw, npw_max, psi);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_pw_to_grid", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_ptrs(p, coef, "coef")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(psi), "psi")) != FOCK_OK) return s;
+    if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
+    return run_pw_to_grid(p, coef, gidx, npw, npw_max, psi);
+  });
 }
 
 fock_status fock_grid_to_pw(fock_plan_t plan, void* const* f, const int32_t* const* gidx, const int32_t* const* npw,
                             const int32_t* npw_max, void* const* coef_out) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(f), "f")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(coef_out), "coef_out")) != FOCK_OK) return s;
-  if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
-  return run_grid_to_pw(p, f, gidx, npw, npw_max, coef_out);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_grid_to_pw", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(f), "f")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(coef_out), "coef_out")) != FOCK_OK) return s;
+    if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
+    return run_grid_to_pw(p, f, gidx, npw, npw_max, coef_out);
+  });
 }
 
 fock_status fock_apply_pw(fock_plan_t plan, const void* const* coef, const int32_t* const* gidx,
@@ -550,34 +684,40 @@ fock_status fock_apply_pw(fock_plan_t plan, const void* const* coef, const int32
                           void* const* psi_work, void* const* vx_work, void* const* vx_coef) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if ((s = check_ptrs(p, coef, "coef")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(psi_work), "psi_work")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_work), "vx_work")) != FOCK_OK) return s;
-  if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_coef), "vx_coef")) != FOCK_OK) return s;
-  if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
-  for (size_t i = 0; i < p->inst.size(); ++i)
-    if (psi_work[i] == vx_work[i]) return set_error(FOCK_ERR_ARG, "psi_work aliases vx_work");
-  if ((s = run_pw_to_grid(p, coef, gidx, npw, npw_max, psi_work)) != FOCK_OK) return s;
-  if ((s = run_apply(p, psi_work, occ, vx_work, nullptr, 1.0, false)) != FOCK_OK) return s;
-  return run_grid_to_pw(p, vx_work, gidx, npw, npw_max, vx_coef);
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_apply_pw", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if ((s = check_ptrs(p, coef, "coef")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(occ), "occ")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(psi_work), "psi_work")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_work), "vx_work")) != FOCK_OK) return s;
+    if ((s = check_ptrs(p, reinterpret_cast<const void* const*>(vx_coef), "vx_coef")) != FOCK_OK) return s;
+    if ((s = check_sphere(p, gidx, npw, npw_max)) != FOCK_OK) return s;
+    for (size_t i = 0; i < p->inst.size(); ++i)
+      if (psi_work[i] == vx_work[i]) return set_error(FOCK_ERR_ARG, "psi_work aliases vx_work");
+    if ((s = run_pw_to_grid(p, coef, gidx, npw, npw_max, psi_work)) != FOCK_OK) return s;
+    if ((s = run_apply(p, psi_work, occ, vx_work, nullptr, 1.0, false)) != FOCK_OK) return s;
+    return run_grid_to_pw(p, vx_work, gidx, npw, npw_max, vx_coef);
+  });
 }
 
 fock_status fock_dft3(fock_plan_t plan, int32_t inst, int32_t sign, int64_t count, void* data, int64_t stride) {
   clear_error();
   Plan* p = reinterpret_cast<Plan*>(plan);
-  fock_status s = check_ready(p);
-  if (s != FOCK_OK) return s;
-  if (inst < 0 || static_cast<size_t>(inst) >= p->inst.size()) return set_error(FOCK_ERR_ARG, "instance out of range");
-  if (sign != -1 && sign != 1) return set_error(FOCK_ERR_ARG, "sign must be -1 or +1");
-  if (count < 0) return set_error(FOCK_ERR_ARG, "count < 0");
-  if (count == 0) return FOCK_OK;
-  if (!data) return set_error(FOCK_ERR_ARG, "data is NULL");
-  if (stride < p->inst[inst].npts) return set_error(FOCK_ERR_ARG, "stride smaller than the grid");
-  const hipError_t e = launch_dft3(*p, inst, sign, count, data, stride);
-  return e == hipSuccess ? FOCK_OK : hip_fail(e, "3-D DFT launch");
+  if (!p) return set_error(FOCK_ERR_ARG, "plan is NULL");
+  return logged(p, "fock_dft3", [&]() -> fock_status {
+    fock_status s = check_ready(p);
+    if (s != FOCK_OK) return s;
+    if (inst < 0 || static_cast<size_t>(inst) >= p->inst.size()) return set_error(FOCK_ERR_ARG, "instance out of range");
+    if (sign != -1 && sign != 1) return set_error(FOCK_ERR_ARG, "sign must be -1 or +1");
+    if (count < 0) return set_error(FOCK_ERR_ARG, "count < 0");
+    if (count == 0) return FOCK_OK;
+    if (!data) return set_error(FOCK_ERR_ARG, "data is NULL");
+    if (stride < p->inst[inst].npts) return set_error(FOCK_ERR_ARG, "stride smaller than the grid");
+    const hipError_t e = launch_dft3(*p, inst, sign, count, data, stride);
+    return e == hipSuccess ? FOCK_OK : hip_fail(e, "3-D DFT launch");
+  });
 }
 
 fock_status fock_plan_stats(fock_plan_t plan, int64_t* ordered_pairs, int64_t* apply_fft_pairs,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,11 @@ struct PairRef {
 //           disjoint orbital blocks); a second accumulate pass gives the
 //           partners their share, conj(W_ab) = W_ba (first_mirror: it writes
 //           them rather than adds), and the pair energies count twice.
+//           tri: outputs and partners are the same block (nO == nP), and the
+//           batch holds its unordered pairs o <= p (npairs = nO (nO + 1) / 2,
+//           row-major over the upper triangle); the accumulate pass takes
+//           conj(W) from the slot (p, o) for p < o, and pairs o != p count
+//           twice in the energy.
 //   energy: an explicit PairRef list at pair_off; its partial sum goes to slot.
 struct Batch {
   int32_t inst = 0;
@@ -36,6 +42,7 @@ struct Batch {
   int32_t first = 0;
   int32_t mirror = 0;
   int32_t first_mirror = 0;
+  int32_t tri = 0;
   size_t pair_off = 0;  // bytes into the workspace
   int32_t npairs = 0;   // pairs in the batch (apply: nO*nP)
   int32_t slot = 0;
@@ -54,6 +61,19 @@ struct FusedGroup {
   int32_t eblk0 = 0;   // first of its nout * nsplit energy partials (apply with energy)
 };
 
+// The unordered band pairs (a, b), a <= b, of one instance on the whole-pair
+// path, as int2 at pairs_off, cut into rounds of pairwise disjoint pairs
+// (round i: pairs round_start[i] .. round_start[i + 1] - 1).  With energy,
+// pair j writes energy partial eblk0 + j; the partials sum into slot eslot.
+struct FusedRounds {
+  int32_t inst = 0;
+  size_t pairs_off = 0;
+  std::vector<int32_t> round_start;
+  int32_t npairs = 0;
+  int32_t eblk0 = 0;
+  int32_t eslot = -1;
+};
+
 struct Instance {
   double lattice[9];
   int grid[3];
@@ -63,6 +83,7 @@ struct Instance {
   bool symmetric = true;                     // (k, k') listed iff (k', k) listed
   bool fused = false;                        // whole-pair path (cubic grid that fits one CU)
   bool reg = false;                          // three-pass path with register-line kernels (N1 x L x L)
+  int rounds = -1;                           // whole-pair path by unordered pairs: its FusedRounds
   int nbands;
   int64_t band_stride;
   double mu;
@@ -89,6 +110,31 @@ struct Profiler {
   void release();
 };
 
+// Call records of a plan (FOCK_LOG): one JSON line per API call with its
+// status, host enqueue time and device time (events around the call on the
+// plan stream), written when the plan is destroyed or the pending records
+// pass a bound, followed at destruction by a per-call summary.
+struct CallLog {
+  struct Rec {
+    const char* call;
+    int status;
+    double enqueue_us;
+    bool graph;
+    hipEvent_t e0, e1;  // null when no device work could be enqueued
+  };
+  FILE* f = nullptr;
+  bool own = false;  // f was opened here (not stderr)
+  uint64_t serial = 0;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  struct Total {
+    int64_t calls = 0;
+    double device_ms = 0.0;
+  };
+  std::vector<std::pair<std::string, Total>> totals;  // per call name, first-use order
+  bool on() const { return f != nullptr; }
+};
+
 // A captured launch sequence and the arguments it was captured with.
 struct GraphCache {
   std::vector<uintptr_t> key;
@@ -110,6 +156,7 @@ struct Plan {
   std::vector<Instance> inst;
   std::vector<Batch> apply_batches, energy_batches;
   std::vector<FusedGroup> fused_groups;
+  std::vector<FusedRounds> fused_rounds;
   // workspace layout (bytes)
   size_t tw_off = 0;                  // twiddle tables
   size_t const_bytes = 0;             // uploaded prefix
@@ -130,6 +177,7 @@ struct Plan {
   size_t max_lds = 0;      // per-block LDS limit of the device
   size_t lds_needed = 0;   // largest dynamic LDS of any launch (+ static)
   mutable Profiler prof;
+  CallLog log;
   bool use_graph = false;
   GraphCache g_apply, g_apply_energy, g_energy, g_backward;
   void release_graphs() {
@@ -138,10 +186,7 @@ struct Plan {
     g_energy.release();
     g_backward.release();
   }
-  ~Plan() {
-    prof.release();
-    release_graphs();
-  }
+  ~Plan();
 };
 
 // status helpers (thread-local last error)
@@ -192,6 +237,13 @@ hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* ps
 hipError_t launch_fused_apply(const Plan& p, const FusedGroup& g, const void* psi, const double* occ, void* out,
                               const double* gscale, double hscale, bool backward, double* eblk);
 hipError_t launch_fused_energy(const Plan& p, const Batch& b, const void* psi);
+// whole-pair path by unordered pairs (FP32 32^3): the grids it serves, and
+// its rounds (outputs zeroed first); eblk: this instance's energy partials or null
+bool fused_rounds_supported(fock_precision prec, const int grid[3]);
+hipError_t launch_fused_rounds(const Plan& p, const FusedRounds& r, const void* psi, const double* occ, void* out,
+                               const double* gscale, double hscale, bool backward, double* eblk);
+// ebsum[slot] = fixed-order sum of n partials at part (FP64)
+hipError_t launch_sum_partials(const Plan& p, const double* part, long long n, int slot);
 hipError_t launch_overlap(const Plan& p, int inst, const void* psi, const void* vx, void* vmat);
 
 }  // namespace fock

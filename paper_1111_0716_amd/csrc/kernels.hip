@@ -520,9 +520,30 @@ hipError_t launch_aslot_finish(const Plan& p, int inst, double* ex) {
   return hipGetLastError();
 }
 
+hipError_t launch_sum_partials(const Plan& p, const double* part, long long n, int slot) {
+  p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
+  hipLaunchKernelGGL(k_sum_slot, dim3(1), dim3(kSumBlock), 0, p.stream, part, n,
+                     reinterpret_cast<double*>(p.ws + p.ebsum_off), slot, 1.0);
+  p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
+  return hipGetLastError();
+}
+
 hipError_t launch_eblk_finish(const Plan& p, int inst, double* ex) {
   const Instance& in = p.inst[inst];
   const double factor = -0.5 * in.omega / static_cast<double>(in.npts);  // as in launch_energy_finish
+  if (in.rounds >= 0) {
+    // one partial per unordered pair: summed in a fixed order into the
+    // instance's slot, then scaled
+    const FusedRounds& r = p.fused_rounds[in.rounds];
+    hipError_t e = launch_sum_partials(p, reinterpret_cast<const double*>(p.ws + p.eblk_off) + r.eblk0, r.npairs,
+                                       r.eslot);
+    if (e != hipSuccess) return e;
+    p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
+    hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(64), 0, p.stream,
+                       reinterpret_cast<const double*>(p.ws + p.ebsum_off), r.eslot, 1, factor, ex);
+    p.prof.end(FOCK_K_ENERGY_REDUCE, p.stream);
+    return hipGetLastError();
+  }
   p.prof.begin(FOCK_K_ENERGY_REDUCE, p.stream);
   hipLaunchKernelGGL(k_energy_finish, dim3(1), dim3(64), 0, p.stream,
                      reinterpret_cast<const double*>(p.ws + p.eblk_off), in.first_eblk, in.n_eblk, factor, ex);

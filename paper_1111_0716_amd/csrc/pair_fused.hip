@@ -469,6 +469,114 @@ __global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused(
 }
 
 // ---------------------------------------------------------------------------
+// apply / backward by unordered pairs: one workgroup per pair of a round
+// ---------------------------------------------------------------------------
+// bo[j] += coef * bm[j] * x[j] (CONJ: * conj(x[j])) over the thread's lines in
+// layout A, in double-buffered batches of kA (u and the output are read
+// together, the sum written back).
+template <typename T, int L, bool CONJ, int kA>
+__device__ __forceinline__ void rmw_accumulate(typename cx<T>::t (*x)[L], const typename cx<T>::t* __restrict__ bm,
+                                               typename cx<T>::t* __restrict__ bo, uint32_t toff, T coef) {
+  using C = typename cx<T>::t;
+  using Sh = FusedShape<T, L>;
+  constexpr int LL = L * L;
+  constexpr int E = Sh::LPT * L;
+  constexpr int NB = E / kA;
+  static_assert(E % kA == 0, "batch size must divide the thread's elements");
+  C mb[2][kA], ob[2][kA];
+#pragma unroll
+  for (int j = 0; j < kA; ++j) {
+    const uint32_t a = toff + (j / L) * (Sh::RPT * LL) + (j % L) * L;
+    mb[0][j] = bm[a];
+    ob[0][j] = bo[a];
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    if (b + 1 < NB) {
+#pragma unroll
+      for (int j = 0; j < kA; ++j) {
+        const int e = (b + 1) * kA + j;
+        const uint32_t a = toff + (e / L) * (Sh::RPT * LL) + (e % L) * L;
+        mb[(b + 1) & 1][j] = bm[a];
+        ob[(b + 1) & 1][j] = bo[a];
+      }
+    }
+    mem_fence_compiler();
+#pragma unroll
+    for (int j = 0; j < kA; ++j) {
+      const int e = b * kA + j;
+      const C u = mb[b & 1][j];
+      const C w = CONJ ? cmulconj(x[e / L][e % L], u) : cmul(u, x[e / L][e % L]);
+      const uint32_t a = toff + (e / L) * (Sh::RPT * LL) + (e % L) * L;
+      bo[a] = cadd(ob[b & 1][j], cscale(w, coef));
+    }
+  }
+}
+
+// One unordered pair (a, b), a <= b (global band indices k nbands + n), per
+// workgroup: W_ab = IDFT(v_q DFT(conj(u_b) u_a)) once, then
+//   out_a += -w_kb f_b F_a u_b W_ab,   out_b += -w_ka f_a F_b u_a conj(W_ab)
+// (W_ba = conj(W_ab): the Nyquist-averaged kernel is even under (c, q) ->
+// (-c, -q)); a == b adds the first only.  F_x is the output factor (hscale,
+// gscale and, for the backward, w_kx f_x).  The pairs of one launch are
+// pairwise disjoint, so no output is written by two workgroups; the outputs
+// were zeroed before the first round.  ENERGY: eblk[pair] = w_a f_a w_b f_b
+// sum_c v/N |P|^2, times 2 when a != b (the pair stands for both orders).
+template <typename T, int L, bool ENERGY = false>
+__global__ __launch_bounds__((FusedShape<T, L>::NT)) void k_pair_fused_sym(
+    int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, const int2* __restrict__ pairs, int nk,
+    const int* __restrict__ qmap, const T* __restrict__ vtab, const double* __restrict__ occ,
+    const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, const double* __restrict__ gscale,
+    double hscale, int backward, double* __restrict__ eblk) {
+  using C = typename cx<T>::t;
+  using Sh = FusedShape<T, L>;
+  static_assert(!Sh::ACC_REG, "pair rounds serve the grids whose output is read-modify-written per pair");
+  constexpr int LL = L * L;
+  constexpr int LPT = Sh::LPT;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ float junk[64];  // landing area of the L2 prefetch (never read)
+  __shared__ double eslot[ENERGY ? Sh::NT : 1];
+  C* s = reinterpret_cast<C*>(smem_raw);
+  const int t = threadIdx.x, row0 = t / L, col = t - (t / L) * L;
+  const int2 pr = pairs[blockIdx.x];
+  const int a = pr.x, b = pr.y;
+  const int ka = a / nbands, kb = b / nbands;
+  double g = hscale;
+  if (gscale) g *= gscale[0];
+  const double fa = backward ? g * kw[ka] * occ[a] : g;
+  const double fb = backward ? g * kw[kb] * occ[b] : g;
+  const size_t npts = static_cast<size_t>(LL) * L;
+  const size_t oa = static_cast<size_t>(a) * bs, ob = static_cast<size_t>(b) * bs;
+  const uint32_t toff0 = static_cast<uint32_t>(row0 * LL + col);  // layout A element (j1 = row0, 0, j3 = col)
+  const T* tab = vtab + static_cast<size_t>(qmap[ka * nk + kb]) * npts;
+  C x[LPT][L];
+  load_codensity<T, L>(x, psi + opaque_idx(ob), psi + opaque_idx(oa), opaque_off(toff0));
+  // warm L2 with the first output (read back after the transforms) and the table
+  fused_forward<T, L>(x, s, row0, col, Prefetch<T>{out + oa, tab, junk});
+  double esum = 0.0;
+  mul_kernel<T, L, ENERGY>(x, tab, opaque_off(static_cast<uint32_t>(t)), esum);
+  if constexpr (ENERGY) eslot[t] = esum;
+  fused_inverse<T, L>(x, s, row0, col);
+  constexpr int kA = ENERGY ? 2 : 4;
+  rmw_accumulate<T, L, false, kA>(x, psi + opaque_idx(ob), out + opaque_idx(oa), opaque_off(toff0),
+                                  static_cast<T>(-kw[kb] * occ[b] * fa));
+  if (a != b)
+    rmw_accumulate<T, L, true, kA>(x, psi + opaque_idx(oa), out + opaque_idx(ob), opaque_off(toff0),
+                                   static_cast<T>(-kw[ka] * occ[a] * fb));
+  if constexpr (ENERGY) {
+    // fixed-order block sum by the first wave: lane l takes l, l + 64, ...
+    __syncthreads();
+    if (t < 64) {
+      double e = 0.0;
+      for (int i = t; i < Sh::NT; i += 64) e += eslot[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+      if (t == 0) eblk[blockIdx.x] = (a != b ? 2.0 : 1.0) * kw[ka] * occ[a] * kw[kb] * occ[b] * e;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // energy: per pair sum_c v_q(c)/N |P(c)|^2 in FP64, `per_wg` pairs per block
 // ---------------------------------------------------------------------------
 template <typename T, int L>
@@ -599,6 +707,36 @@ hipError_t fused_apply_L(const Plan& p, const FusedGroup& g, const void* psi, co
   return hipGetLastError();
 }
 
+// The rounds of unordered pairs of one instance (outputs zeroed first).
+template <typename T, int L>
+hipError_t fused_rounds_L(const Plan& p, const FusedRounds& r, const void* psi, const double* occ, void* out,
+                          const double* gscale, double hscale, bool backward, double* eblk) {
+  using C = typename cx<T>::t;
+  using Sh = FusedShape<T, L>;
+  const Instance& in = p.inst[r.inst];
+  const size_t lds = static_cast<size_t>(Sh::LDS) * sizeof(C);
+  hipError_t e = launch_zero_all_bands(p, r.inst, out);
+  if (e != hipSuccess) return e;
+  const int2* pairs = reinterpret_cast<const int2*>(p.ws + r.pairs_off);
+  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
+  const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
+  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
+  for (size_t i = 0; i + 1 < r.round_start.size(); ++i) {
+    const int p0 = r.round_start[i], n = r.round_start[i + 1] - p0;
+    p.prof.begin(FOCK_K_FUSED, p.stream);
+    if (eblk)
+      hipLaunchKernelGGL((k_pair_fused_sym<T, L, true>), dim3(n), dim3(Sh::NT), lds, p.stream, in.nbands,
+                         static_cast<long long>(in.band_stride), static_cast<const C*>(psi), pairs + p0, in.nk, qmap,
+                         vtab, occ, kw, static_cast<C*>(out), gscale, hscale, backward ? 1 : 0, eblk + p0);
+    else
+      hipLaunchKernelGGL((k_pair_fused_sym<T, L, false>), dim3(n), dim3(Sh::NT), lds, p.stream, in.nbands,
+                         static_cast<long long>(in.band_stride), static_cast<const C*>(psi), pairs + p0, in.nk, qmap,
+                         vtab, occ, kw, static_cast<C*>(out), gscale, hscale, backward ? 1 : 0, nullptr);
+    p.prof.end(FOCK_K_FUSED, p.stream);
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int L>
 hipError_t fused_energy_L(const Plan& p, const Batch& b, const void* psi) {
   using C = typename cx<T>::t;
@@ -654,9 +792,26 @@ void fused_lds_attr(int lim) {
                       reinterpret_cast<const void*>(&k_pair_energy_fused<T, L>)};
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+  if constexpr (!FusedShape<T, L>::ACC_REG) {
+    const void* fr[] = {reinterpret_cast<const void*>(&k_pair_fused_sym<T, L, false>),
+                        reinterpret_cast<const void*>(&k_pair_fused_sym<T, L, true>)};
+    for (const void* f : fr)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess)
+        (void)hipGetLastError();
+  }
 }
 
 }  // namespace
+
+bool fused_rounds_supported(fock_precision prec, const int grid[3]) {
+  return prec == FOCK_C64 && grid[0] == 32 && grid[1] == 32 && grid[2] == 32 && !FusedShape<float, 32>::ACC_REG;
+}
+
+hipError_t launch_fused_rounds(const Plan& p, const FusedRounds& r, const void* psi, const double* occ, void* out,
+                               const double* gscale, double hscale, bool backward, double* eblk) {
+  if (p.prec != FOCK_C64 || p.inst[r.inst].grid[0] != 32) return hipErrorInvalidValue;
+  return fused_rounds_L<float, 32>(p, r, psi, occ, out, gscale, hscale, backward, eblk);
+}
 
 bool fused_supported(fock_precision prec, const int grid[3]) {
   if (grid[0] != grid[1] || grid[0] != grid[2]) return false;

@@ -67,6 +67,28 @@ __host__ __device__ constexpr int batch_of(int L, int want) {
   return b;
 }
 
+// Output and partner slots (o, p) of pair slot pi of an apply batch: pi =
+// o nP + p, or for a block paired with itself (tri) the unordered pairs
+// o <= p, row-major over the upper triangle (row o starts at tri_slot(o, o)).
+__host__ __device__ constexpr size_t tri_slot(int o, int p, int n) {
+  return static_cast<size_t>(o) * n - static_cast<size_t>(o) * (o - 1) / 2 + static_cast<size_t>(p - o);
+}
+
+__device__ __forceinline__ void batch_pair(int pi, int nP, int tri, int* o, int* p) {
+  if (!tri) {
+    *o = pi / nP;
+    *p = pi - *o * nP;
+    return;
+  }
+  const double b = 2.0 * nP + 1.0;
+  int r = static_cast<int>((b - sqrt(b * b - 8.0 * pi)) * 0.5);
+  r = r < 0 ? 0 : (r > nP - 1 ? nP - 1 : r);
+  while (r > 0 && tri_slot(r, r, nP) > static_cast<size_t>(pi)) --r;
+  while (r + 1 < nP && tri_slot(r + 1, r + 1, nP) <= static_cast<size_t>(pi)) ++r;
+  *o = r;
+  *p = r + static_cast<int>(static_cast<size_t>(pi) - tri_slot(r, r, nP));
+}
+
 // complex value in another precision
 template <typename C, typename CI>
 __device__ __forceinline__ C cvt(CI v) {
@@ -204,7 +226,7 @@ __device__ __forceinline__ void transpose_plane(C* x, T* sp, int col) {
 // wide operands fit beside the line without spilling)
 template <typename T, int L, bool EXPLICIT, typename TI = T>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? RegShape<T, L>::WPE_PLANE : 1)) void k_plane_reg(
-    int n1, int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP,
+    int n1, int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP, int tri,
     const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
@@ -220,7 +242,8 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? R
     okn = pr.k * nbands + pr.n;
     pkm = pr.kp * nbands + pr.m;
   } else {
-    const int o = pi / nP, p = pi - o * nP;
+    int o, p;
+    batch_pair(pi, nP, tri, &o, &p);
     okn = o0 + o;
     const int2 r = parts[p];
     pkm = r.x * nbands + r.y;
@@ -278,14 +301,15 @@ __device__ __forceinline__ void pencil_apply_line(int l, int LL, int pi, int q, 
 
 template <typename T, int L, bool EN = false>
 __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_apply_reg(int ll, int nbands, int nk, int o0, int nP,
-                                                          const int2* __restrict__ parts, const int* __restrict__ qmap,
+                                                          int tri, const int2* __restrict__ parts, const int* __restrict__ qmap,
                                                           typename cx<T>::t* __restrict__ tbuf,
                                                           const T* __restrict__ vtab, const double* __restrict__ occ,
                                                           const double* __restrict__ kw, double* __restrict__ epart) {
   const int LL = ll;  // lines per pair (N2 N3); L is the line length N1
   const int l = blockIdx.x * 256 + threadIdx.x;  // line (c3, c2) = l
   const int pi = blockIdx.y;
-  const int o = pi / nP, p = pi - o * nP;
+  int o, p;
+  batch_pair(pi, nP, tri, &o, &p);
   const int ok = (o0 + o) / nbands;
   const int2 r = parts[p];
   const int q = qmap[ok * nk + r.x];
@@ -295,7 +319,9 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_ap
   } else {
     double e = 0.0;
     if (l < LL) pencil_apply_line<T, L, true>(l, LL, pi, q, tbuf, vtab, &e);
-    store_line_energy(e, kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y], epart);
+    // an unordered pair of a block with itself stands for both orders
+    store_line_energy(e, (tri && o != p ? 2.0 : 1.0) * kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y],
+                      epart);
   }
 }
 
@@ -337,35 +363,44 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_PENCIL)) void k_pencil_en
 // ---------------------------------------------------------------------------
 // accumulate pass: per (output, plane group), every partner of the batch
 // ---------------------------------------------------------------------------
-// Batch pairs are pi = o nP + p (output o0 + o, partner parts[p]).
-//   MIRROR false: blockIdx.y = o; W of pair (o, p) for every p, times u_p.
-//   MIRROR true:  blockIdx.y = p, the partner is the output; for every o the
-//                 pair's W_{o p} gives W_{p o} = conj(W_{o p}), times u_{o0+o}.
-// The global band index of the orbital that multiplies W, and the pair slot.
-template <bool MIRROR>
-__device__ __forceinline__ void acc_source(int j, int blk, int o0, int nP, int nbands, const int2* __restrict__ parts,
-                                           int* band, size_t* pair) {
-  if (MIRROR) {
+// Batch pairs are pi = o nP + p (output o0 + o, partner parts[p]).  One
+// launch serves the batch's outputs (blockIdx.y = o < nO) and, for a batch of
+// unordered pairs of two blocks (mirror), also its partners (blockIdx.y =
+// nO + p): the outputs are disjoint, so the two halves never write the same
+// band.
+//   output o:    W of pair (o, p) for every p, times u_p.
+//   partner p:   the partner is the output; for every o the pair's W_{o p}
+//                gives W_{p o} = conj(W_{o p}), times u_{o0+o}.
+//   tri (a block paired with itself, unordered pairs o <= p at tri_slot):
+//                 output o takes W_{o p} from slot (o, p) for p >= o and
+//                 conj(W_{p o}) from slot (p, o) for p < o.
+// The global band index of the orbital that multiplies W, the pair slot, and
+// whether the slot holds the conjugate of the W wanted.
+__device__ __forceinline__ void acc_source(bool mirror, int j, int blk, int o0, int nP, int tri, int nbands,
+                                           const int2* __restrict__ parts, int* band, size_t* pair, bool* cj) {
+  if (mirror) {
     *band = o0 + j;
     *pair = static_cast<size_t>(j) * nP + blk;
+    *cj = true;
   } else {
     const int2 r = parts[j];
     *band = r.x * nbands + r.y;
-    *pair = static_cast<size_t>(blk) * nP + j;
+    if (tri) {
+      *pair = j >= blk ? tri_slot(blk, j, nP) : tri_slot(j, blk, nP);
+      *cj = j < blk;
+    } else {
+      *pair = static_cast<size_t>(blk) * nP + j;
+      *cj = false;
+    }
   }
 }
 
-// u W (or u conj(W) for the mirror pass)
-template <bool MIRROR, typename C>
-__device__ __forceinline__ C acc_term(C u, C w) {
-  return MIRROR ? cmulconj(w, u) : cmul(u, w);
-}
-
-template <typename T, int L, bool MIRROR = false>
+template <typename T, int L>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) void k_acc_reg(
-    int n1, int nbands, long long bs, int o0, int nO, int nP, const int2* __restrict__ parts,
+    int n1, int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    int first_mirror,
     const double* __restrict__ gscale, double hscale, int backward) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
@@ -377,8 +412,9 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int j1 = blockIdx.x * Sh::PL + pl;
   const bool valid = j1 < n1;
-  const int o = blockIdx.y;
-  const int nsrc = MIRROR ? nO : nP;
+  const bool mirror = static_cast<int>(blockIdx.y) >= nO;
+  const int o = mirror ? static_cast<int>(blockIdx.y) - nO : static_cast<int>(blockIdx.y);
+  const int nsrc = mirror ? nO : nP;
   sp += pl * L * Sh::LP;
   C acc[L];
 #pragma unroll
@@ -386,7 +422,8 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   for (int p = 0; p < nsrc; ++p) {
     int sb;
     size_t pair;
-    acc_source<MIRROR>(p, o, o0, nP, nbands, parts, &sb, &pair);
+    bool cj;
+    acc_source(mirror, p, o, o0, nP, tri, nbands, parts, &sb, &pair, &cj);
     C x[L];
     if (valid) {
       const C* src = tbuf + pair * LL * n1 + static_cast<size_t>(j1) * LL + col;
@@ -399,6 +436,10 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
     reg_fft<C, L, +1>(x);                   // inverse axis 3: x[j3] at (j1, c2 = col)
     transpose_plane<C, T, L>(x, sp, col);   // column (j1, j3 = col)
     reg_fft<C, L, +1>(x);                   // inverse axis 2: x[j2]
+    if (cj) {
+#pragma unroll
+      for (int j2 = 0; j2 < L; ++j2) x[j2].y = -x[j2].y;
+    }
     if (valid) {
       const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
       const C* um = psi + static_cast<size_t>(sb) * bs + static_cast<size_t>(j1) * LL + col;
@@ -414,7 +455,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
         reg_fence();
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-          const C w = acc_term<MIRROR>(mb[n & 1][j], x[n * B + j]);
+          const C w = cmul(mb[n & 1][j], x[n * B + j]);
           acc[n * B + j].x += coef * w.x;
           acc[n * B + j].y += coef * w.y;
         }
@@ -422,13 +463,13 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
     }
   }
   if (!valid) return;  // no barrier after this point
-  const int okn = MIRROR ? parts[o].x * nbands + parts[o].y : o0 + o;
+  const int okn = mirror ? parts[o].x * nbands + parts[o].y : o0 + o;
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[okn / nbands] * occ[okn];
   const T ft = static_cast<T>(f);
   C* dst = out + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
-  if (!first) {
+  if (!(mirror ? first_mirror : first)) {
     // every earlier value is loaded before the first store, so the loads
     // overlap instead of waiting one by one behind the stores
     C old[L];
@@ -540,7 +581,7 @@ __device__ __forceinline__ void transpose_split(C* y, T* sp, int col, int h) {
 
 template <typename T, int L, bool EXPLICIT>
 __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LINE)) void k_plane_split(
-    int n1, int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP,
+    int n1, int nbands, long long bs, const typename cx<T>::t* __restrict__ psi, int o0, int nP, int tri,
     const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
@@ -556,7 +597,8 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LIN
     okn = pr.k * nbands + pr.n;
     pkm = pr.kp * nbands + pr.m;
   } else {
-    const int o = pi / nP, p = pi - o * nP;
+    int o, p;
+    batch_pair(pi, nP, tri, &o, &p);
     okn = o0 + o;
     const int2 r = parts[p];
     pkm = r.x * nbands + r.y;
@@ -602,7 +644,7 @@ __device__ __forceinline__ void pencil_apply_split_line(int l, int h, int LL, in
 
 template <typename T, int L, bool EN = false>
 __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_apply_split(
-    int ll, int nbands, int nk, int o0, int nP, const int2* __restrict__ parts, const int* __restrict__ qmap,
+    int ll, int nbands, int nk, int o0, int nP, int tri, const int2* __restrict__ parts, const int* __restrict__ qmap,
     typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab, const double* __restrict__ occ,
     const double* __restrict__ kw, double* __restrict__ epart) {
   using Sh = SplitShape<T, L>;
@@ -610,7 +652,8 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_ap
   const int h = threadIdx.x & 1;
   const int l = blockIdx.x * Sh::LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
   const int pi = blockIdx.y;
-  const int o = pi / nP, p = pi - o * nP;
+  int o, p;
+  batch_pair(pi, nP, tri, &o, &p);
   const int ok = (o0 + o) / nbands;
   const int2 r = parts[p];
   const int q = qmap[ok * nk + r.x];
@@ -620,7 +663,8 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_ap
   } else {
     double e = 0.0;  // each lane: its half of the spectrum
     if (l < LL) pencil_apply_split_line<T, L, true>(l, h, LL, pi, q, tbuf, vtab, &e);
-    store_line_energy(e, kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y], epart);
+    store_line_energy(e, (tri && o != p ? 2.0 : 1.0) * kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y],
+                      epart);
   }
 }
 
@@ -660,11 +704,12 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_en
   if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-template <typename T, int L, bool MIRROR = false>
+template <typename T, int L>
 __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC)) void k_acc_split(
-    int n1, int nbands, long long bs, int o0, int nO, int nP, const int2* __restrict__ parts,
+    int n1, int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    int first_mirror,
     const double* __restrict__ gscale, double hscale, int backward) {
   using C = typename cx<T>::t;
   using Sh = SplitShape<T, L>;
@@ -675,18 +720,20 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
   const int j1 = blockIdx.x * Sh::PL + pl;
   const bool valid = j1 < n1;
-  const int o = blockIdx.y;
+  const bool mirror = static_cast<int>(blockIdx.y) >= nO;
+  const int o = mirror ? static_cast<int>(blockIdx.y) - nO : static_cast<int>(blockIdx.y);
   T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
   // element (j1, 2m + h, col) of a grid: the lane's samples along axis 2
   const size_t eo = static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * L + col;
-  const int nsrc = MIRROR ? nO : nP;
+  const int nsrc = mirror ? nO : nP;
   C acc[LH];
 #pragma unroll
   for (int m = 0; m < LH; ++m) acc[m] = C{T(0), T(0)};
   for (int p = 0; p < nsrc; ++p) {
     int sb;
     size_t pair;
-    acc_source<MIRROR>(p, o, o0, nP, nbands, parts, &sb, &pair);
+    bool cj;
+    acc_source(mirror, p, o, o0, nP, tri, nbands, parts, &sb, &pair, &cj);
     C y[LH];
     if (valid) {
       const C* src = tbuf + pair * LL * n1 + static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * LH * L + col;
@@ -699,6 +746,10 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
     split_fft_inv<C, L>(y, h);                      // inverse axis 3: y[m] at j3 = 2m + h
     transpose_split<C, T, L, true>(y, sp, col, h);  // column j3 = col, c2 = h L/2 + k
     split_fft_inv<C, L>(y, h);                      // inverse axis 2: y[m] at j2 = 2m + h
+    if (cj) {
+#pragma unroll
+      for (int m = 0; m < LH; ++m) y[m].y = -y[m].y;
+    }
     if (valid) {
       const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
       const C* um = psi + static_cast<size_t>(sb) * bs + eo;
@@ -714,7 +765,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
         reg_fence();
 #pragma unroll
         for (int j = 0; j < B; ++j) {
-          const C w = acc_term<MIRROR>(mb[n & 1][j], y[n * B + j]);
+          const C w = cmul(mb[n & 1][j], y[n * B + j]);
           acc[n * B + j].x += coef * w.x;
           acc[n * B + j].y += coef * w.y;
         }
@@ -722,13 +773,13 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
     }
   }
   if (!valid) return;  // no barrier after this point
-  const int okn = MIRROR ? parts[o].x * nbands + parts[o].y : o0 + o;
+  const int okn = mirror ? parts[o].x * nbands + parts[o].y : o0 + o;
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[okn / nbands] * occ[okn];
   const T ft = static_cast<T>(f);
   C* dst = out + static_cast<size_t>(okn) * bs + eo;
-  if (!first) {
+  if (!(mirror ? first_mirror : first)) {
     C old[LH];  // loaded before the first store (see k_acc_reg)
 #pragma unroll
     for (int m = 0; m < LH; ++m) old[m] = dst[m * 2 * L];
@@ -771,7 +822,7 @@ __device__ __forceinline__ void pencil_apply_mixed_line(int l, int h, int LL, in
 // EN: the energy variant (see k_pencil_apply_reg), from the FP32 forward
 // spectrum widened to FP64
 template <int L, bool EN = false>
-__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nbands, int nk, int o0, int nP,
+__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nbands, int nk, int o0, int nP, int tri,
                                                                const int2* __restrict__ parts,
                                                                const int* __restrict__ qmap,
                                                                const float2* __restrict__ t32,
@@ -785,7 +836,8 @@ __global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nband
   const int h = threadIdx.x & 1;
   const int l = blockIdx.x * LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
   const int pi = blockIdx.y;
-  const int o = pi / nP, p = pi - o * nP;
+  int o, p;
+  batch_pair(pi, nP, tri, &o, &p);
   const int ok = (o0 + o) / nbands;
   const int2 r = parts[p];
   const int q = qmap[ok * nk + r.x];
@@ -795,7 +847,8 @@ __global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nband
   } else {
     double e = 0.0;
     if (l < LL) pencil_apply_mixed_line<L, true>(l, h, LL, pi, q, t32, t64, vtab, &e);
-    store_line_energy(e, kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y], epart);
+    store_line_energy(e, (tri && o != p ? 2.0 : 1.0) * kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y],
+                      epart);
   }
 }
 
@@ -832,19 +885,19 @@ void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void*
   using Po = RegPolicy<T, L>;
   const int n1 = in.grid[0];
   const long long bs = static_cast<long long>(in.band_stride);
-  const int o0 = EXPLICIT ? 0 : b.o0, nP = EXPLICIT ? 1 : b.nP;
+  const int o0 = EXPLICIT ? 0 : b.o0, nP = EXPLICIT ? 1 : b.nP, tri = EXPLICIT ? 0 : b.tri;
   if constexpr (sizeof(TI) != sizeof(T)) {  // FOCK_MIXED: one-lane FP32 lines from FP64 orbitals
     using Sh = RegShape<T, L>;
     hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
-                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const CI*>(psi), o0, nP, parts, pairs, tbuf);
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const CI*>(psi), o0, nP, tri, parts, pairs, tbuf);
   } else if constexpr (Po::SPLIT_PLANE) {
     using Sh = SplitShape<T, L>;
     hipLaunchKernelGGL((k_plane_split<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
-                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, tri, parts, pairs, tbuf);
   } else {
     using Sh = RegShape<T, L>;
     hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
-                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, parts, pairs, tbuf);
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, tri, parts, pairs, tbuf);
   }
 }
 
@@ -858,19 +911,19 @@ int launch_pencil_apply(const Plan& p, const Batch& b, const Instance& in, const
     const int nlb = (ll + SplitShape<T, L>::LPB - 1) / SplitShape<T, L>::LPB;
     if (epart)
       hipLaunchKernelGGL((k_pencil_apply_split<T, L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
-                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+                         in.nbands, in.nk, b.o0, b.nP, b.tri, parts, qmap, tbuf, vtab, occ, kw, epart);
     else
       hipLaunchKernelGGL((k_pencil_apply_split<T, L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
-                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+                         in.nbands, in.nk, b.o0, b.nP, b.tri, parts, qmap, tbuf, vtab, occ, kw, epart);
     return nlb;
   } else {
     const int nlb = (ll + 255) / 256;
     if (epart)
       hipLaunchKernelGGL((k_pencil_apply_reg<T, L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
-                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+                         in.nbands, in.nk, b.o0, b.nP, b.tri, parts, qmap, tbuf, vtab, occ, kw, epart);
     else
       hipLaunchKernelGGL((k_pencil_apply_reg<T, L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll,
-                         in.nbands, in.nk, b.o0, b.nP, parts, qmap, tbuf, vtab, occ, kw, epart);
+                         in.nbands, in.nk, b.o0, b.nP, b.tri, parts, qmap, tbuf, vtab, occ, kw, epart);
     return nlb;
   }
 }
@@ -893,36 +946,27 @@ int launch_pencil_energy(const Plan& p, const Batch& b, const Instance& in, cons
   }
 }
 
-// mirror: the batch's partners are the outputs (see k_acc_reg)
-template <typename T, int L, bool MIRROR = false>
-void launch_acc(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
-                const void* psi, const double* occ, const double* kw, void* out, const double* gscale, double hscale,
-                bool backward) {
-  using C = typename cx<T>::t;
-  const int n1 = in.grid[0];
-  const long long bs = static_cast<long long>(in.band_stride);
-  const int nout = MIRROR ? b.nP : b.nO;
-  const int first = MIRROR ? b.first_mirror : b.first;
-  if constexpr (RegPolicy<T, L>::SPLIT_ACC) {
-    using Sh = SplitShape<T, L>;
-    hipLaunchKernelGGL((k_acc_split<T, L, MIRROR>), dim3((n1 + Sh::PL - 1) / Sh::PL, nout), dim3(Sh::NTP), Sh::LDS,
-                       p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
-                       static_cast<C*>(out), first, gscale, hscale, backward ? 1 : 0);
-  } else {
-    using Sh = RegShape<T, L>;
-    hipLaunchKernelGGL((k_acc_reg<T, L, MIRROR>), dim3((n1 + Sh::PL - 1) / Sh::PL, nout), dim3(Sh::NTP), Sh::LDS,
-                       p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, parts, tbuf, static_cast<const C*>(psi), occ, kw,
-                       static_cast<C*>(out), first, gscale, hscale, backward ? 1 : 0);
-  }
-}
-
-// the accumulate pass of a batch, and its mirror pass for unordered pairs
+// the accumulate pass of a batch: its outputs, and for a batch of unordered
+// pairs of two blocks also its partners (see k_acc_reg)
 template <typename T, int L>
 void launch_acc_all(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
                     const void* psi, const double* occ, const double* kw, void* out, const double* gscale,
                     double hscale, bool backward) {
-  launch_acc<T, L, false>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale, backward);
-  if (b.mirror) launch_acc<T, L, true>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale, backward);
+  using C = typename cx<T>::t;
+  const int n1 = in.grid[0];
+  const long long bs = static_cast<long long>(in.band_stride);
+  const int rows = b.nO + (b.mirror ? b.nP : 0);
+  if constexpr (RegPolicy<T, L>::SPLIT_ACC) {
+    using Sh = SplitShape<T, L>;
+    hipLaunchKernelGGL((k_acc_split<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS, p.stream,
+                       n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi), occ, kw,
+                       static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
+  } else {
+    using Sh = RegShape<T, L>;
+    hipLaunchKernelGGL((k_acc_reg<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS, p.stream,
+                       n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi), occ, kw,
+                       static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
+  }
 }
 
 template <typename T, int L>
@@ -936,13 +980,11 @@ void reg_lds_attr(int lim) {
     fs[0] = reinterpret_cast<const void*>(&k_plane_reg<T, L, false>);
     fs[1] = reinterpret_cast<const void*>(&k_plane_reg<T, L, true>);
   }
-  if constexpr (Po::SPLIT_ACC) {
-    fs[2] = reinterpret_cast<const void*>(&k_acc_split<T, L, false>);
-    fs[3] = reinterpret_cast<const void*>(&k_acc_split<T, L, true>);
-  } else {
-    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L, false>);
-    fs[3] = reinterpret_cast<const void*>(&k_acc_reg<T, L, true>);
-  }
+  if constexpr (Po::SPLIT_ACC)
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<T, L>);
+  else
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L>);
+  fs[3] = fs[2];
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
@@ -964,10 +1006,10 @@ int launch_pencil_mixed(const Plan& p, const Batch& b, const Instance& in, const
   const int nlb = (ll + 127) / 128;
   if (epart)
     hipLaunchKernelGGL((k_pencil_apply_mixed<L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, in.nbands,
-                       in.nk, b.o0, b.nP, parts, qmap, t32, t64, vtab, occ, kw, epart);
+                       in.nk, b.o0, b.nP, b.tri, parts, qmap, t32, t64, vtab, occ, kw, epart);
   else
     hipLaunchKernelGGL((k_pencil_apply_mixed<L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, in.nbands,
-                       in.nk, b.o0, b.nP, parts, qmap, t32, t64, vtab, occ, kw, epart);
+                       in.nk, b.o0, b.nP, b.tri, parts, qmap, t32, t64, vtab, occ, kw, epart);
   return nlb;
 }
 
@@ -976,13 +1018,11 @@ void mixed_lds_attr(int lim) {
   using Acc = RegPolicy<double, L>;
   const void* fs[4] = {reinterpret_cast<const void*>(&k_plane_reg<float, L, false, double>),
                        reinterpret_cast<const void*>(&k_plane_reg<float, L, true, double>), nullptr, nullptr};
-  if constexpr (Acc::SPLIT_ACC) {
-    fs[2] = reinterpret_cast<const void*>(&k_acc_split<double, L, false>);
-    fs[3] = reinterpret_cast<const void*>(&k_acc_split<double, L, true>);
-  } else {
-    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L, false>);
-    fs[3] = reinterpret_cast<const void*>(&k_acc_reg<double, L, true>);
-  }
+  if constexpr (Acc::SPLIT_ACC)
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<double, L>);
+  else
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L>);
+  fs[3] = fs[2];
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }

@@ -113,6 +113,78 @@ bool full_kset(const Instance& in) {
   return true;
 }
 
+// The unordered pairs (a, b), a <= b, of the listed k-pairs (orbital a =
+// k nbands + n), in rounds of at most `cap` pairwise disjoint pairs.  Source
+// order: the n - 1 perfect matchings of the circle method on the orbitals
+// (a dummy orbital makes the count even), then the self pairs; each pair goes
+// first-fit into the oldest of a few open rounds that has room and neither of
+// its orbitals, so nearly every round is full.  pairs: (a, b) flattened;
+// starts: first pair of every round and the total at the end.
+void build_rounds(const Instance& in, int cap, std::vector<int32_t>& pairs, std::vector<int32_t>& starts) {
+  const int nb = in.nbands, O = in.nk * nb, n = O + (O & 1);
+  std::vector<char> listed(static_cast<size_t>(in.nk) * in.nk, 0);
+  for (int k = 0; k < in.nk; ++k)
+    for (int kp : in.kpartners[k]) listed[static_cast<size_t>(k) * in.nk + kp] = 1;
+  struct Round {
+    std::vector<int32_t> p;
+    std::vector<char> used;
+  };
+  constexpr size_t kWindow = 8;
+  std::vector<Round> open;  // oldest first
+  auto close_oldest = [&]() {
+    starts.push_back(static_cast<int32_t>(pairs.size() / 2));
+    pairs.insert(pairs.end(), open.front().p.begin(), open.front().p.end());
+    open.erase(open.begin());
+  };
+  auto place = [&](int a, int b) {
+    if (a > b) std::swap(a, b);
+    if (!listed[static_cast<size_t>(a / nb) * in.nk + b / nb]) return;
+    for (Round& r : open)
+      if (static_cast<int>(r.p.size() / 2) < cap && !r.used[a] && !r.used[b]) {
+        r.p.push_back(a);
+        r.p.push_back(b);
+        r.used[a] = r.used[b] = 1;
+        return;
+      }
+    if (open.size() == kWindow) close_oldest();
+    open.push_back(Round{{a, b}, std::vector<char>(O, 0)});
+    open.back().used[a] = open.back().used[b] = 1;
+  };
+  for (int r = 0; r + 1 < n; ++r) {
+    if (n - 1 < O) place(r, n - 1);  // the fixed vertex (absent when it is the dummy)
+    for (int i = 1; i < n / 2; ++i) place((r + i) % (n - 1), (r - i + (n - 1)) % (n - 1));
+  }
+  for (int a = 0; a < O; ++a) place(a, a);
+  while (!open.empty()) close_oldest();
+  starts.push_back(static_cast<int32_t>(pairs.size() / 2));
+}
+
+// The schedule's contract, checked on the host: every listed unordered pair
+// exactly once, no orbital twice within a round.
+bool rounds_valid(const Instance& in, const std::vector<int32_t>& pairs, const std::vector<int32_t>& starts) {
+  const int nb = in.nbands, O = in.nk * nb;
+  std::vector<char> listed(static_cast<size_t>(in.nk) * in.nk, 0);
+  for (int k = 0; k < in.nk; ++k)
+    for (int kp : in.kpartners[k]) listed[static_cast<size_t>(k) * in.nk + kp] = 1;
+  std::vector<char> seen(static_cast<size_t>(O) * O, 0);
+  std::vector<int32_t> last_round(O, -1);
+  for (size_t r = 0; r + 1 < starts.size(); ++r) {
+    for (int32_t j = starts[r]; j < starts[r + 1]; ++j) {
+      const int a = pairs[2 * j], b = pairs[2 * j + 1];
+      if (a < 0 || b >= O || a > b) return false;
+      if (last_round[a] == static_cast<int32_t>(r) || last_round[b] == static_cast<int32_t>(r)) return false;
+      last_round[a] = last_round[b] = static_cast<int32_t>(r);
+      char& s = seen[static_cast<size_t>(a) * O + b];
+      if (s) return false;
+      s = 1;
+    }
+  }
+  for (int a = 0; a < O; ++a)
+    for (int b = a; b < O; ++b)
+      if (seen[static_cast<size_t>(a) * O + b] != listed[static_cast<size_t>(a / nb) * in.nk + b / nb]) return false;
+  return true;
+}
+
 size_t env_mb(const char* name, size_t dflt) {
   const char* s = std::getenv(name);
   if (!s || !*s) return dflt;
@@ -158,7 +230,7 @@ fock_status validate_desc(const fock_desc& d, int idx) {
 
 fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, void* stream, const fock_tuning* tune,
                        Plan** out) {
-  const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0, 0};
+  const fock_tuning tn = tune ? *tune : fock_tuning{0, 0, 0, 0, 0, 0};
   static std::atomic<uint64_t> next_serial{1};
   auto p = std::make_unique<Plan>();
   p->serial = next_serial.fetch_add(1);
@@ -230,8 +302,16 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const bool no_reg = noreg && *noreg && *noreg != '0';
   const char* nosym = std::getenv("FOCK_NO_PAIR_SYMMETRY");
   const bool no_sym = tn.no_pair_symmetry != 0 || (nosym && *nosym && *nosym != '0');
+  const char* rounds_env = std::getenv("FOCK_FUSED_ROUNDS");
+  const bool use_rounds = tn.fused_rounds != 0 || (rounds_env && *rounds_env && *rounds_env != '0');
   for (auto& in : p->inst) {
-    in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused;
+    // The 32^3 FP32 whole-pair kernel read-modify-writes its output per
+    // partner; with the full k-pair set the three-pass path with pair
+    // symmetry moves fewer bytes per ordered pair and is faster (alpha boron
+    // 416 against 606 ms per step), so it takes those instances.
+    const bool sym_three_pass = !no_sym && !use_rounds && fused_rounds_supported(prec, in.grid) && full_kset(in) &&
+                                reg_supported(prec, in.grid) && !no_reg;
+    in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused && !sym_three_pass;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
     if (prec == FOCK_MIXED && !in.reg)
       return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 36, 40, 48, 50, 54, 60, 64, 72}");
@@ -281,11 +361,34 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   size_t max_pairs_elems = 0;  // max over batches of npairs * npts
   size_t max_partial = 0;      // bytes of partial sums of the whole-pair path
   const int n_cus = static_cast<int>(env_mb("FOCK_CUS", 256));
+  // whole-pair path by unordered pairs (the grids whose output is
+  // read-modify-written per pair anyway), on request: rounds of two
+  // workgroups per CU
+  std::vector<std::vector<int32_t>> round_pairs;
+  for (int i = 0; i < n_inst; ++i) {
+    Instance& in = p->inst[i];
+    if (!(use_rounds && in.fused && in.symmetric && fused_rounds_supported(prec, in.grid))) continue;
+    FusedRounds r;
+    r.inst = i;
+    std::vector<int32_t> pl;
+    build_rounds(in, static_cast<int>(env_mb("FOCK_ROUND_PAIRS", 2 * static_cast<size_t>(n_cus))), pl, r.round_start);
+    if (!rounds_valid(in, pl, r.round_start))
+      return set_error(FOCK_ERR_UNSUPPORTED, "instance " + std::to_string(i) + ": internal error in the pair rounds");
+    r.npairs = static_cast<int32_t>(pl.size() / 2);
+    if (r.npairs == 0) continue;
+    r.pairs_off = off;
+    off = align_up(off + pl.size() * sizeof(int32_t));
+    in.rounds = static_cast<int>(p->fused_rounds.size());
+    p->fused_rounds.push_back(std::move(r));
+    round_pairs.push_back(std::move(pl));
+    p->apply_fft_pairs += p->fused_rounds.back().npairs;
+  }
   for (const Group& g : groups) {
     const Instance& in = p->inst[g.inst];
     const int nout = (g.k1 - g.k0) * in.nbands;
     const int npart = static_cast<int>(g.parts.size() / 2);
     if (npart == 0) continue;
+    if (in.rounds >= 0) continue;  // served by its rounds
     if (in.fused) {
       FusedGroup fg;
       fg.inst = g.inst;
@@ -320,9 +423,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       // in c -> -c, q -> -q), so each unordered pair is transformed once.  The
       // orbitals (partner order = global order k' nbands + m) are cut into
       // blocks of bs; block pair (I, J), I < J, is one batch whose accumulate
-      // pass serves I and whose mirror pass serves J; the pairs inside a block
-      // run as an ordinary batch.  Batches run in sequence on one stream, so
-      // no output is written by two launches at once.
+      // pass serves I and whose mirror pass serves J; a block with itself is a
+      // triangular batch of its unordered pairs.  Batches run in sequence on
+      // one stream, so no output is written by two launches at once.
       int bs = std::max(1, std::min(nout, static_cast<int>(std::sqrt(static_cast<double>(pmax)))));
       const int nblk = (nout + bs - 1) / bs;
       bs = (nout + nblk - 1) / nblk;
@@ -343,8 +446,11 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
             b.mirror = 1;
             b.first_mirror = touched[J] ? 0 : 1;
             touched[J] = 1;
+            b.npairs = ni * nj;
+          } else {
+            b.tri = 1;  // the block with itself: its unordered pairs once
+            b.npairs = ni * (ni + 1) / 2;
           }
-          b.npairs = ni * nj;
           max_pairs_elems = std::max(max_pairs_elems, static_cast<size_t>(b.npairs) * in.npts);
           p->apply_batches.push_back(b);
           p->apply_fft_pairs += b.npairs;
@@ -464,6 +570,12 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
       g.eblk0 = neblk;
       neblk += g.nout * g.nsplit;
     }
+    for (FusedRounds& r : p->fused_rounds) {
+      if (r.inst != i) continue;
+      r.eblk0 = neblk;
+      neblk += r.npairs;
+      r.eslot = slot++;
+    }
     p->inst[i].n_eblk = neblk - p->inst[i].first_eblk;
   }
   p->eblk_off = off;
@@ -481,8 +593,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     p->lds_needed = std::max(p->lds_needed, need);
   }
   p->apply_launches = 0;
-  for (const Batch& b : p->apply_batches) p->apply_launches += b.mirror ? 4 : 3;
+  for (const Batch& b : p->apply_batches) p->apply_launches += 3;
   for (const FusedGroup& g : p->fused_groups) p->apply_launches += g.nsplit > 1 ? 2 : 1;
+  for (const FusedRounds& r : p->fused_rounds) p->apply_launches += static_cast<int64_t>(r.round_start.size());
 
   // ---- host image of the constant prefix ----
   p->host_image.assign(p->const_bytes, 0);
@@ -543,6 +656,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   }
   for (const Group& g : groups)
     if (!g.parts.empty()) std::memcpy(img + g.off, g.parts.data(), g.parts.size() * sizeof(int32_t));
+  for (size_t i = 0; i < p->fused_rounds.size(); ++i)
+    std::memcpy(img + p->fused_rounds[i].pairs_off, round_pairs[i].data(), round_pairs[i].size() * sizeof(int32_t));
   for (int i = 0; i < n_inst; ++i) {
     const Instance& in = p->inst[i];
     if (in.n_ebatches == 0) continue;

@@ -40,7 +40,7 @@ class FockError(RuntimeError):
 
 class FockTuning(ctypes.Structure):
     _fields_ = [("acc_workgroups", c_int32), ("tbuf_mb", c_int32), ("fused_split", c_int32), ("no_fused", c_int32),
-                ("no_pair_symmetry", c_int32)]
+                ("no_pair_symmetry", c_int32), ("fused_rounds", c_int32)]
 
 
 class FockDesc(ctypes.Structure):

@@ -36,8 +36,8 @@ def _plan_with(tuning, grid=(32, 32, 32), nb=4, prec=fock.FOCK_C64):
 
 
 def test_tuning_knobs_change_the_schedule():
-    st0, h0 = _plan_with({})
-    st1, h1 = _plan_with({"no_fused": 1, "acc_workgroups": 64})
+    st0, h0 = _plan_with({"no_pair_symmetry": 1})  # the whole-pair kernel, one workgroup per output
+    st1, h1 = _plan_with({"no_fused": 1, "acc_workgroups": 64, "no_pair_symmetry": 1})
     assert st0 == fock.FOCK_OK and st1 == fock.FOCK_OK
     a0, a1 = ctypes.c_int64(), ctypes.c_int64()
     L = fock.lib()
@@ -52,5 +52,23 @@ def test_tuning_knobs_change_the_schedule():
 def test_tuning_knob_validation():
     st, _ = _plan_with({"fused_split": 9})
     assert st == fock.FOCK_ERR_ARG
+    st, _ = _plan_with({"fused_rounds": 2})
+    assert st == fock.FOCK_ERR_ARG
     st, _ = _plan_with({"tbuf_mb": -1})
     assert st == fock.FOCK_ERR_ARG
+
+
+def test_candidates_cover_the_joint_grid_and_collapse_equal_schedules():
+    c = autotune.candidates({"plane", "pencil", "accumulate"})
+    assert {} in c
+    assert any(t.get("tbuf_mb") == 256 and "no_pair_symmetry" not in t for t in c)  # Infinity-Cache-sized batches
+    ordered = {(t["tbuf_mb"], t["acc_workgroups"]) for t in c if t.get("no_pair_symmetry")}
+    assert ordered == {(tb, aw) for tb in autotune.ORDERED_TBUF_MB for aw in autotune.ORDERED_ACC_WORKGROUPS}
+    f = autotune.candidates({"fused"})
+    assert {t.get("fused_split") for t in f if "fused_split" in t} == {1, 2, 3, 4}
+    assert {"fused_rounds": 1} in f
+    # a tiny three-pass instance: every pair-buffer budget gives the same plan
+    inst = dict(lattice=inputs.cubic_lattice(10.0), grid=(24, 32, 32), kfrac=np.zeros((1, 3)), nbands=2)
+    sigs = {autotune.plan_signature([inst], "c64", t) for t in c}
+    assert len(sigs) < len(c)
+    assert autotune.plan_signature([inst], "c64", {}) == autotune.plan_signature([inst], "c64", {"tbuf_mb": 128})

@@ -103,3 +103,11 @@ def test_cpu_baseline_uses_every_usable_core_on_a_tiny_instance():
 def test_host_info_fields():
     h = bench.host_info()
     assert h["nproc"] >= 1 and h["cpus_usable"] >= 1 and "cpu_model" in h and "rocm" in h
+
+
+def test_launch_gaps_are_the_step_time_outside_kernels():
+    r = {"ms_per_step": 100.0, "kernels": {"plane": (40.0, 10), "pencil": (30.0, 10), "accumulate": (20.0, 20)}}
+    g = bench.launch_gaps(r)
+    assert g["launches_per_step"] == 40 and g["kernel_ms_per_step"] == 90.0
+    assert g["idle_ms_per_step"] == pytest.approx(10.0) and g["idle_frac"] == pytest.approx(0.1)
+    assert g["idle_us_per_launch"] == pytest.approx(250.0)

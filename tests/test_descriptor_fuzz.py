@@ -55,7 +55,8 @@ def _random_case(rng):
     if rng.uniform() < 0.5:
         tn = fock.FockTuning(acc_workgroups=int(rng.integers(-1, 4000)), tbuf_mb=int(rng.integers(-1, 64)),
                              fused_split=int(rng.integers(-1, 6)), no_fused=int(rng.integers(0, 2)),
-                             no_pair_symmetry=int(rng.integers(0, 2)))
+                             no_pair_symmetry=int(rng.integers(0, 2)),
+                             fused_rounds=int(rng.integers(-1, 3)) if rng.uniform() < 0.2 else int(rng.integers(0, 2)))
     return d, keep, prec, tn, kpairs, nk, nbands
 
 
