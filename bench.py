@@ -682,6 +682,9 @@ def main():
                     help="timed steps of the beta-boron 72^3 leg of the default run (0: skip it)")
     ap.add_argument("--workload", choices=["alpha", "beta", "diff", "ragged", "fft3d", "pw", "precision", "membw"],
                     default="alpha")
+    ap.add_argument("--bands", type=int, default=0,
+                    help="--workload beta|diff: keep only the first N bands of every k (a smaller run of the same "
+                         "kernels, e.g. for counter collection); 0: all")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (the reference dispatch "
                          "that scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -710,6 +713,9 @@ def main():
     cfg = {"alpha": "2", "beta": "3", "diff": "5"}[args.workload]
     log(f"generating inputs: preset {cfg} ({WORKLOADS[cfg]})")
     inst = inputs.config(cfg, dtype=np.complex128, workers=16)
+    if args.bands and args.workload != "alpha":
+        inst = inputs.band_subset(inst, args.bands)
+        log(f"  first {inst.nbands} bands of every k")
     inst32 = inst.astype(np.complex64)
     cb = None
     if not args.no_cpu_baseline:

@@ -214,6 +214,14 @@ def config(cfg_id, dtype=None, workers=None):
     return inst
 
 
+def band_subset(inst, nbands):
+    """The instance restricted to the first `nbands` bands of every k."""
+    nb = max(1, min(int(nbands), inst.nbands))
+    return Instance(inst.lattice, inst.grid, inst.kfrac, inst.kweight, np.ascontiguousarray(inst.occ[:, :nb]),
+                    np.ascontiguousarray(inst.psi[:, :nb]), inst.mu, inst.ecut, f"{inst.name}-first{nb}",
+                    dict(inst.extra))
+
+
 def uneven_batch_params(n_inst=48, seed=4):
     """Shapes of the ragged batch: per instance (cell, grid, k-mesh, bands, E_cut)."""
     rng = np.random.default_rng([SEED_BASE, seed, 999_999])

@@ -58,3 +58,11 @@ def test_uneven_batch_params_reproducible():
     for a, b in zip(p1, p2):
         assert a["grid"] == b["grid"] and a["nbands"] == b["nbands"] and a["kmesh"] == b["kmesh"]
         assert 8 <= a["nbands"] <= 96 and a["grid"][0] in (24, 32, 40, 48, 64)
+
+
+def test_band_subset_keeps_the_first_bands():
+    inst = inputs.small_instance(grid=(8, 6, 10), kmesh=(2, 1, 1), nbands=5, seed=(330, 0))
+    sub = inputs.band_subset(inst, 3)
+    assert sub.nbands == 3 and sub.nk == inst.nk
+    assert np.array_equal(sub.psi, inst.psi[:, :3]) and np.array_equal(sub.occ, inst.occ[:, :3])
+    assert sub.psi.flags["C_CONTIGUOUS"]
