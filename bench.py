@@ -119,15 +119,18 @@ def dominant_apply(kern):
     return max(cands, key=lambda c: c[1])
 
 
-def roofline(kern, stats, grid, s, peak_tflops, traffic=None):
+def roofline(kern, stats, grid, s, peak_tflops, traffic=None, workload=None):
     """Roofline entry of the unit with the largest share of the profiled step.
     ``traffic``: counter bytes per launch of that unit (None if not measured
-    for the current sources)."""
+    for the current sources); with ``workload`` it is read from that
+    workload's committed traffic summaries instead."""
     model = kernel_model(grid, s)
     units = _units(stats)
     dom, tot_ms, launches = dominant_apply(kern)
     mk = "energy_fused" if dom == "energy_fused" else "fused"  # the three passes are one apply
     nunits = units["fused"] if dom == THREE_PASS_UNIT else units[dom]
+    if workload is not None:
+        traffic = unit_traffic(workload, dom, kern, nunits / launches)
     per_launch_ms = tot_ms / launches
     flops = model[mk]["flops"] * nunits / launches
     byts = model[mk]["bytes"] * nunits / launches
@@ -152,24 +155,21 @@ def roofline(kern, stats, grid, s, peak_tflops, traffic=None):
     return roof
 
 
-def unit_traffic(workload, dom, kern=None):
+def unit_traffic(workload, dom, kern=None, units_per_launch=None):
     """Counter bytes per launch of the dominant unit from the committed
-    traffic summaries, or None.  The three-pass unit is one batch: its plane
-    and pencil dispatch plus its accumulate dispatches (two for a batch of
-    unordered pairs: the mirror pass), each kind's bytes per dispatch times
-    its dispatches per batch in the step (`kern`)."""
+    traffic summaries, or None.  Each summary gives bytes per unit of work
+    (per ordered pair: bytes per dispatch over the ordered pairs per batch of
+    the counted run), so a run whose batches are larger or smaller than the
+    counted one's is scaled by its own units per launch."""
     pattern = TRAFFIC_FILES.get(workload)
     if not pattern:
         return None
     from paper_1111_0716_amd.profile_summary import read_traffic
     kinds = THREE_PASS if dom == THREE_PASS_UNIT else (dom,)
-    vals = [read_traffic(os.path.join(ROOT, pattern.format(kind=k)), k) for k in kinds]
-    if any(v is None for v in vals):
+    vals = [read_traffic(os.path.join(ROOT, pattern.format(kind=k)), k, per_unit=True) for k in kinds]
+    if any(v is None for v in vals) or not units_per_launch:
         return None
-    if dom == THREE_PASS_UNIT and kern:
-        batches = kern["plane"][1]
-        return sum(v * kern[k][1] / batches for k, v in zip(kinds, vals))
-    return sum(vals)
+    return sum(vals) * units_per_launch
 
 
 def kernel_rates(kern, stats, grid, s):
@@ -748,7 +748,7 @@ def main():
     value = pairs / (r32["ms_per_step"] / 1e3)
     dom = dominant_apply(r32["kernels"])[0]
     roof = roofline(r32["kernels"], r32["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
-                    traffic=unit_traffic(args.workload, dom, r32["kernels"]))
+                    workload=args.workload if not args.bands else None)
     copy_gbs = copy_bandwidth(device)
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["hbm_frac_vs_copy"] = round(roof["alt"]["hbm_gbs"] / copy_gbs, 4)
@@ -842,8 +842,7 @@ def beta_leg(args, device):
     log(f"  {r['ms_per_step']:.1f} ms/step")
     pairs = r["stats"]["ordered_pairs"]
     dom = dominant_apply(r["kernels"])[0]
-    roof = roofline(r["kernels"], r["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"],
-                    traffic=unit_traffic("beta", dom, r["kernels"]))
+    roof = roofline(r["kernels"], r["stats"], inst.grid, 8, VALU_PEAK_TFLOPS["c64"], workload="beta")
     return {"workload": WORKLOADS["3"], "ordered_pairs_per_step": pairs, "steps": args.beta_steps, "warmup": w,
             "ms_per_step": round(r["ms_per_step"], 3), "pairs_per_s": round(pairs / (r["ms_per_step"] / 1e3), 1),
             "roofline": roof, "launch_gaps": launch_gaps(r),

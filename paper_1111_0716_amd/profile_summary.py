@@ -144,6 +144,7 @@ def traffic_summary(a, argv):
              f"fetch_bytes_per_launch: {fb:.6e}",
              f"write_bytes_per_launch: {wb:.6e}",
              f"traffic_bytes_per_launch: {total:.6e}",
+             f"units_per_launch: {a.units_per_launch:.6e}",
              f"sources_sha256: {sources_sha256(a.kind)}", ""]
     return "\n".join(lines)
 
@@ -191,9 +192,11 @@ def counters_summary(dirs, kernel, title, commands):
     return "\n".join(lines) + "\n"
 
 
-def read_traffic(path, kind):
-    """Scaled HBM bytes per launch from a traffic summary, or None when the
-    file is absent or the kernel's sources changed since it was taken."""
+def read_traffic(path, kind, per_unit=False):
+    """Scaled HBM bytes per launch from a traffic summary (per unit of work
+    when `per_unit`: per launch divided by the units per launch the summary
+    was taken with), or None when the file is absent or the kernel's sources
+    changed since it was taken."""
     try:
         with open(path) as f:
             kv = dict(re.findall(r"^(\w+): (\S+)$", f.read(), flags=re.M))
@@ -201,7 +204,12 @@ def read_traffic(path, kind):
         return None
     if kv.get("kind") != kind or kv.get("sources_sha256") != sources_sha256(kind):
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    b = float(kv["traffic_bytes_per_launch"])
+    if per_unit:
+        if "units_per_launch" not in kv:
+            return None
+        return b / float(kv["units_per_launch"])
+    return b
 
 
 def main(argv=None):
