@@ -621,15 +621,17 @@ def precision(args):
     occ = torch.from_numpy(inst.occ).to(device)
     psi = {"c64": torch.from_numpy(inst.psi.astype(np.complex64)).to(device),
            "c128": torch.from_numpy(inst.psi).to(device)}
-    psi["mixed"] = psi["c128"]
-    plans = {pr: fock.Plan([inst], precision=pr, device=device) for pr in ("c64", "c128", "mixed")}
+    psi["mixed"] = psi["mixed_inv"] = psi["c128"]
+    plans = {pr: fock.Plan([inst], precision=pr, device=device) for pr in ("c64", "c128", "mixed", "mixed_inv")}
     m = plans["c128"].meta[0]
     scale = 2.0 * m["omega"] / m["npts"]
     gex = torch.ones(1, dtype=torch.float64, device=device)
     policies = {"all FP64": ("c128", "c128", "c128"), "all FP32": ("c64", "c64", "c64"),
                 "FP32 apply and backward, FP64 energy": ("c64", "c128", "c64"),
                 "mixed in every call (FP32 co-density and forward, FP64 multiply, inverse, accumulate)":
-                    ("mixed", "mixed", "mixed")}
+                    ("mixed", "mixed", "mixed"),
+                "the other mixed policy in every call (FP64 co-density, forward, multiply and energy; FP32 "
+                "inverse and accumulate)": ("mixed_inv", "mixed_inv", "mixed_inv")}
     rows, ref = {}, None
     for name, (pa, pe, pb) in list(policies.items()):
         def step():

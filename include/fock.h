@@ -68,15 +68,21 @@ typedef enum {
 } fock_status;
 
 /* FOCK_C128: complex128 throughout.  FOCK_C64: complex64 orbitals, FP32
- * arithmetic (FP64 tables, twiddles and energy sums).  FOCK_MIXED: complex128
- * orbitals and outputs; co-densities and forward transforms in FP32, kernel
- * multiply, inverse transforms and accumulate in FP64 (the paper's "some of
- * the FFTs in single precision"); grids N1 x L x L with N1 and L each 24,
- * 32, 36, 40, 48, 50, 54, 60, 64 or 72 only (FOCK_ERR_UNSUPPORTED otherwise). */
+ * arithmetic (FP64 tables, twiddles and energy sums).  The two mixed
+ * policies (the paper's "some of the FFTs in single precision") take
+ * complex128 orbitals and outputs:
+ *   FOCK_MIXED      co-densities and forward transforms in FP32; kernel
+ *                   multiply, inverse transforms and accumulate in FP64
+ *   FOCK_MIXED_INV  co-densities, forward transforms, kernel multiply and
+ *                   pair energies in FP64; inverse transforms and the
+ *                   accumulate in FP32 (added into the FP64 outputs in FP64)
+ * Both need grids N1 x L x L with N1 and L each 24, 32, 36, 40, 48, 50, 54,
+ * 60, 64 or 72 (FOCK_ERR_UNSUPPORTED otherwise). */
 typedef enum {
   FOCK_C128 = 0,
   FOCK_C64 = 1,
   FOCK_MIXED = 2,
+  FOCK_MIXED_INV = 3,
   FOCK_PRECISION_RANGE_MIN_ = -2147483647 - 1, /* not precisions (see fock_status) */
   FOCK_PRECISION_RANGE_MAX_ = 2147483647
 } fock_precision;

@@ -427,7 +427,8 @@ fock_status fock_plan_tuned(const fock_desc* descs, int32_t n_inst, fock_precisi
   if (!out) return set_error(FOCK_ERR_ARG, "out is NULL");
   if (!descs) return set_error(FOCK_ERR_ARG, "descs is NULL");
   if (n_inst < 1) return set_error(FOCK_ERR_ARG, "n_inst < 1");
-  if (prec != FOCK_C128 && prec != FOCK_C64 && prec != FOCK_MIXED) return set_error(FOCK_ERR_ARG, "unknown precision");
+  if (prec != FOCK_C128 && prec != FOCK_C64 && prec != FOCK_MIXED && prec != FOCK_MIXED_INV)
+    return set_error(FOCK_ERR_ARG, "unknown precision");
   for (int i = 0; i < n_inst; ++i) {
     const fock_status s = validate_desc(descs[i], i);
     if (s != FOCK_OK) return s;

@@ -395,14 +395,15 @@ __device__ __forceinline__ void acc_source(bool mirror, int j, int blk, int o0, 
   }
 }
 
-template <typename T, int L>
+template <typename T, int L, typename TI = T>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) void k_acc_reg(
     int n1, int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
-    const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
-    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    const typename cx<T>::t* __restrict__ tbuf, const typename cx<TI>::t* __restrict__ psi,
+    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<TI>::t* __restrict__ out, int first,
     int first_mirror,
     const double* __restrict__ gscale, double hscale, int backward) {
   using C = typename cx<T>::t;
+  using CI = typename cx<TI>::t;  // orbitals and outputs (wider than the transform for FOCK_MIXED_INV)
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
   constexpr int B = batch_of(L, Sh::ACC_B);
@@ -442,15 +443,15 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
     }
     if (valid) {
       const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
-      const C* um = psi + static_cast<size_t>(sb) * bs + static_cast<size_t>(j1) * LL + col;
+      const CI* um = psi + static_cast<size_t>(sb) * bs + static_cast<size_t>(j1) * LL + col;
       C mb[2][B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) mb[0][j] = um[j * L];
+      for (int j = 0; j < B; ++j) mb[0][j] = cvt<C>(um[j * L]);
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
         if (n + 1 < NB) {
 #pragma unroll
-          for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = um[((n + 1) * B + j) * L];
+          for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = cvt<C>(um[((n + 1) * B + j) * L]);
         }
         reg_fence();
 #pragma unroll
@@ -467,19 +468,35 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[okn / nbands] * occ[okn];
-  const T ft = static_cast<T>(f);
-  C* dst = out + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
-  if (!(mirror ? first_mirror : first)) {
-    // every earlier value is loaded before the first store, so the loads
-    // overlap instead of waiting one by one behind the stores
-    C old[L];
+  CI* dst = out + static_cast<size_t>(okn) * bs + static_cast<size_t>(j1) * LL + col;
+  const bool add = !(mirror ? first_mirror : first);
+  if constexpr (sizeof(TI) != sizeof(T)) {
+    // wide outputs: scaled in FP64 and read-modify-written in batches
+    constexpr int OB = batch_of(L, 8);
 #pragma unroll
-    for (int j2 = 0; j2 < L; ++j2) old[j2] = dst[j2 * L];
+    for (int n = 0; n < L / OB; ++n) {
+      CI old[OB];
 #pragma unroll
-    for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cadd(old[j2], cscale(acc[j2], ft));
+      for (int j = 0; j < OB; ++j) old[j] = add ? dst[(n * OB + j) * L] : CI{TI(0), TI(0)};
+#pragma unroll
+      for (int j = 0; j < OB; ++j)
+        dst[(n * OB + j) * L] = CI{old[j].x + f * static_cast<TI>(acc[n * OB + j].x),
+                                   old[j].y + f * static_cast<TI>(acc[n * OB + j].y)};
+    }
   } else {
+    const T ft = static_cast<T>(f);
+    if (add) {
+      // every earlier value is loaded before the first store, so the loads
+      // overlap instead of waiting one by one behind the stores
+      C old[L];
 #pragma unroll
-    for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cscale(acc[j2], ft);
+      for (int j2 = 0; j2 < L; ++j2) old[j2] = dst[j2 * L];
+#pragma unroll
+      for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cadd(old[j2], cscale(acc[j2], ft));
+    } else {
+#pragma unroll
+      for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cscale(acc[j2], ft);
+    }
   }
 }
 
@@ -704,14 +721,15 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_en
   if (threadIdx.x == 0) epart[static_cast<size_t>(pi) * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-template <typename T, int L>
+template <typename T, int L, typename TI = T>
 __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC)) void k_acc_split(
     int n1, int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
-    const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
-    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    const typename cx<T>::t* __restrict__ tbuf, const typename cx<TI>::t* __restrict__ psi,
+    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<TI>::t* __restrict__ out, int first,
     int first_mirror,
     const double* __restrict__ gscale, double hscale, int backward) {
   using C = typename cx<T>::t;
+  using CI = typename cx<TI>::t;  // orbitals and outputs (wider than the transform for FOCK_MIXED_INV)
   using Sh = SplitShape<T, L>;
   constexpr int LL = L * L, LH = Sh::LH;
   constexpr int B = batch_of(LH, Sh::WPE_ACC == 1 ? 16 : kRegB);
@@ -752,15 +770,15 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
     }
     if (valid) {
       const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
-      const C* um = psi + static_cast<size_t>(sb) * bs + eo;
+      const CI* um = psi + static_cast<size_t>(sb) * bs + eo;
       C mb[2][B];
 #pragma unroll
-      for (int j = 0; j < B; ++j) mb[0][j] = um[j * 2 * L];
+      for (int j = 0; j < B; ++j) mb[0][j] = cvt<C>(um[j * 2 * L]);
 #pragma unroll
       for (int n = 0; n < NB; ++n) {
         if (n + 1 < NB) {
 #pragma unroll
-          for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = um[((n + 1) * B + j) * 2 * L];
+          for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = cvt<C>(um[((n + 1) * B + j) * 2 * L]);
         }
         reg_fence();
 #pragma unroll
@@ -777,17 +795,33 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   double f = hscale;
   if (gscale) f *= gscale[0];
   if (backward) f *= kw[okn / nbands] * occ[okn];
-  const T ft = static_cast<T>(f);
-  C* dst = out + static_cast<size_t>(okn) * bs + eo;
-  if (!(mirror ? first_mirror : first)) {
-    C old[LH];  // loaded before the first store (see k_acc_reg)
+  CI* dst = out + static_cast<size_t>(okn) * bs + eo;
+  const bool add = !(mirror ? first_mirror : first);
+  if constexpr (sizeof(TI) != sizeof(T)) {
+    // wide outputs: scaled in FP64 and read-modify-written in batches
+    constexpr int OB = batch_of(LH, 8);
 #pragma unroll
-    for (int m = 0; m < LH; ++m) old[m] = dst[m * 2 * L];
+    for (int n = 0; n < LH / OB; ++n) {
+      CI old[OB];
 #pragma unroll
-    for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cadd(old[m], cscale(acc[m], ft));
+      for (int j = 0; j < OB; ++j) old[j] = add ? dst[(n * OB + j) * 2 * L] : CI{TI(0), TI(0)};
+#pragma unroll
+      for (int j = 0; j < OB; ++j)
+        dst[(n * OB + j) * 2 * L] = CI{old[j].x + f * static_cast<TI>(acc[n * OB + j].x),
+                                       old[j].y + f * static_cast<TI>(acc[n * OB + j].y)};
+    }
   } else {
+    const T ft = static_cast<T>(f);
+    if (add) {
+      C old[LH];  // loaded before the first store (see k_acc_reg)
 #pragma unroll
-    for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cscale(acc[m], ft);
+      for (int m = 0; m < LH; ++m) old[m] = dst[m * 2 * L];
+#pragma unroll
+      for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cadd(old[m], cscale(acc[m], ft));
+    } else {
+#pragma unroll
+      for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cscale(acc[m], ft);
+    }
   }
 }
 
@@ -847,6 +881,67 @@ __global__ __launch_bounds__(256, 1) void k_pencil_apply_mixed(int ll, int nband
   } else {
     double e = 0.0;
     if (l < LL) pencil_apply_mixed_line<L, true>(l, h, LL, pi, q, t32, t64, vtab, &e);
+    store_line_energy(e, (tri && o != p ? 2.0 : 1.0) * kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y],
+                      epart);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the other mixed precision (FOCK_MIXED_INV): pencil pass from the FP64 pair
+// buffer to the FP32 one: forward axis 1, kernel multiply (and the pair
+// energies) in FP64, inverse axis 1 in FP32
+// ---------------------------------------------------------------------------
+template <int L, bool EN>
+__device__ __forceinline__ void pencil_apply_mixinv_line(int l, int h, int LL, int pi, int q,
+                                                         const double2* __restrict__ t64, float2* __restrict__ t32,
+                                                         const double* __restrict__ vtab, double* es) {
+  constexpr int LH = L / 2;
+  const size_t base = static_cast<size_t>(pi) * LL * L;
+  const unsigned le = static_cast<unsigned>(h) * LL + l;  // lane's element offset
+  float2 f[LH];
+  {
+    double2 y[LH];
+#pragma unroll
+    for (int m = 0; m < LH; ++m) y[m] = *lane_at(t64 + base + static_cast<size_t>(2 * m) * LL, le * 16u);  // j1 = 2m + h
+    split_fft_fwd<double2, L>(y, h);  // y[k] at c1 = h L/2 + k
+    mul_table_line_u<double2, double, LH, EN>(y, vtab + static_cast<size_t>(q) * LL * L,
+                                              opaque((static_cast<unsigned>(h) * LH * LL + l) * 8u), LL, es);
+#pragma unroll
+    for (int k = 0; k < LH; ++k) f[k] = cvt<float2>(y[k]);
+  }
+  split_fft_inv<float2, L>(f, h);
+  const unsigned so = opaque(le * 8u);
+#pragma unroll
+  for (int m = 0; m < LH; ++m) *lane_at(t32 + base + static_cast<size_t>(2 * m) * LL, so) = f[m];
+}
+
+// EN: the energy variant (see k_pencil_apply_reg), from the FP64 spectrum
+template <int L, bool EN = false>
+__global__ __launch_bounds__(256, 1) void k_pencil_apply_mixinv(int ll, int nbands, int nk, int o0, int nP, int tri,
+                                                                const int2* __restrict__ parts,
+                                                                const int* __restrict__ qmap,
+                                                                const double2* __restrict__ t64,
+                                                                float2* __restrict__ t32,
+                                                                const double* __restrict__ vtab,
+                                                                const double* __restrict__ occ,
+                                                                const double* __restrict__ kw,
+                                                                double* __restrict__ epart) {
+  const int LL = ll;
+  constexpr int LPB = 128;
+  const int h = threadIdx.x & 1;
+  const int l = blockIdx.x * LPB + (threadIdx.x >> 1);  // line (c3, c2), shared by the lane pair
+  const int pi = blockIdx.y;
+  int o, p;
+  batch_pair(pi, nP, tri, &o, &p);
+  const int ok = (o0 + o) / nbands;
+  const int2 r = parts[p];
+  const int q = qmap[ok * nk + r.x];
+  if constexpr (!EN) {
+    if (l >= LL) return;  // uniform over the pair; no barrier in this variant
+    pencil_apply_mixinv_line<L, false>(l, h, LL, pi, q, t64, t32, vtab, nullptr);
+  } else {
+    double e = 0.0;
+    if (l < LL) pencil_apply_mixinv_line<L, true>(l, h, LL, pi, q, t64, t32, vtab, &e);
     store_line_energy(e, (tri && o != p ? 2.0 : 1.0) * kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y],
                       epart);
   }
@@ -946,27 +1041,43 @@ int launch_pencil_energy(const Plan& p, const Batch& b, const Instance& in, cons
   }
 }
 
-// the accumulate pass of a batch: its outputs, and for a batch of unordered
-// pairs of two blocks also its partners (see k_acc_reg)
-template <typename T, int L>
-void launch_acc_all(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
-                    const void* psi, const double* occ, const double* kw, void* out, const double* gscale,
-                    double hscale, bool backward) {
-  using C = typename cx<T>::t;
+// the lane-pair accumulate where the one-lane kernel would need too many
+// registers: RegPolicy's choice, and for FP32 sums over FP64 orbitals and
+// outputs (FOCK_MIXED_INV, whose wide operands add registers) from 40 up
+template <typename T, int L, typename TI>
+constexpr bool split_acc() {
+  return sizeof(TI) != sizeof(T) ? L >= 40 : RegPolicy<T, L>::SPLIT_ACC;
+}
+
+template <typename T, int L, typename TI, bool SPLIT>
+void launch_acc_kernel(const Plan& p, const Batch& b, const Instance& in, const int2* parts,
+                       const typename cx<T>::t* tbuf, const void* psi, const double* occ, const double* kw, void* out,
+                       const double* gscale, double hscale, bool backward) {
+  using C = typename cx<TI>::t;
   const int n1 = in.grid[0];
   const long long bs = static_cast<long long>(in.band_stride);
   const int rows = b.nO + (b.mirror ? b.nP : 0);
-  if constexpr (RegPolicy<T, L>::SPLIT_ACC) {
+  if constexpr (SPLIT) {
     using Sh = SplitShape<T, L>;
-    hipLaunchKernelGGL((k_acc_split<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS, p.stream,
-                       n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi), occ, kw,
-                       static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
+    hipLaunchKernelGGL((k_acc_split<T, L, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS,
+                       p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi),
+                       occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
   } else {
     using Sh = RegShape<T, L>;
-    hipLaunchKernelGGL((k_acc_reg<T, L>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS, p.stream,
-                       n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi), occ, kw,
-                       static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
+    hipLaunchKernelGGL((k_acc_reg<T, L, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS,
+                       p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi),
+                       occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
   }
+}
+
+// the accumulate pass of a batch: its outputs, and for a batch of unordered
+// pairs of two blocks also its partners (see k_acc_reg)
+template <typename T, int L, typename TI = T>
+void launch_acc_all(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const typename cx<T>::t* tbuf,
+                    const void* psi, const double* occ, const double* kw, void* out, const double* gscale,
+                    double hscale, bool backward) {
+  launch_acc_kernel<T, L, TI, split_acc<T, L, TI>()>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale,
+                                                     backward);
 }
 
 template <typename T, int L>
@@ -1027,6 +1138,48 @@ void mixed_lds_attr(int lim) {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
 }
 
+// FOCK_MIXED_INV: FP64 plane pass, mixed pencil pass, FP32 accumulate pass
+// reading FP64 orbitals and writing FP64 outputs
+template <int L>
+struct MixInvPolicy {
+  static constexpr int ACC_LDS = L >= 40 ? SplitShape<float, L>::LDS : RegShape<float, L>::LDS;
+  static constexpr int LDS = RegPolicy<double, L>::PLANE_LDS > ACC_LDS ? RegPolicy<double, L>::PLANE_LDS : ACC_LDS;
+};
+
+template <int L>
+int launch_pencil_mixinv(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
+                         const double2* t64, float2* t32, const double* vtab, const double* occ, const double* kw,
+                         double* epart) {
+  const int ll = in.grid[1] * in.grid[2];
+  const int nlb = (ll + 127) / 128;
+  if (epart)
+    hipLaunchKernelGGL((k_pencil_apply_mixinv<L, true>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, in.nbands,
+                       in.nk, b.o0, b.nP, b.tri, parts, qmap, t64, t32, vtab, occ, kw, epart);
+  else
+    hipLaunchKernelGGL((k_pencil_apply_mixinv<L, false>), dim3(nlb, b.npairs), dim3(256), 0, p.stream, ll, in.nbands,
+                       in.nk, b.o0, b.nP, b.tri, parts, qmap, t64, t32, vtab, occ, kw, epart);
+  return nlb;
+}
+
+template <int L>
+void mixinv_lds_attr(int lim) {
+  const void* fs[4] = {nullptr, nullptr, nullptr, nullptr};
+  if constexpr (RegPolicy<double, L>::SPLIT_PLANE) {
+    fs[0] = reinterpret_cast<const void*>(&k_plane_split<double, L, false>);
+    fs[1] = reinterpret_cast<const void*>(&k_plane_split<double, L, true>);
+  } else {
+    fs[0] = reinterpret_cast<const void*>(&k_plane_reg<double, L, false>);
+    fs[1] = reinterpret_cast<const void*>(&k_plane_reg<double, L, true>);
+  }
+  if constexpr (split_acc<float, L, double>())
+    fs[2] = reinterpret_cast<const void*>(&k_acc_split<float, L, double>);
+  else
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<float, L, double>);
+  fs[3] = fs[2];
+  for (const void* f : fs)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+}
+
 // the axis lengths with register-line kernels
 #define FOCK_REG_L(X) X(24) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72)
 
@@ -1082,13 +1235,14 @@ hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const dou
   return hipGetLastError();
 }
 
+// tbuf_off: the pair buffer (0: the plan's at tbuf_off)
 template <typename T>
-hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ) {
+hipError_t reg_energy_t(const Plan& p, const Batch& b, const void* psi, const double* occ, size_t tbuf_off = 0) {
   using C = typename cx<T>::t;
   const Instance& in = p.inst[b.inst];
   const PairRef* pairs = reinterpret_cast<const PairRef*>(p.ws + b.pair_off);
   const T* vtab = reinterpret_cast<const T*>(p.ws + in.vtab_off);
-  C* tbuf = reinterpret_cast<C*>(p.ws + p.tbuf_off);
+  C* tbuf = reinterpret_cast<C*>(p.ws + (tbuf_off ? tbuf_off : p.tbuf_off));
   double* epart = reinterpret_cast<double*>(p.ws + p.epart_off);
   bool ok;
   int nlb = 0;
@@ -1131,6 +1285,39 @@ hipError_t mixed_apply_t(const Plan& p, const Batch& b, const void* psi, const d
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
   ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc_all<double, N>(p, b, in, parts, t64, psi, occ, kw, out, gscale,
                                                                  hscale, backward)));
+  p.prof.end(FOCK_K_ACCUMULATE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t mixinv_apply_t(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
+                          const double* gscale, double hscale, bool backward, bool energy) {
+  const Instance& in = p.inst[b.inst];
+  const int2* parts = reinterpret_cast<const int2*>(p.ws + b.part_off);
+  const int* qmap = reinterpret_cast<const int*>(p.ws + in.qmap_off);
+  const double* vtab = reinterpret_cast<const double*>(p.ws + in.vtab_off);
+  const double* kw = reinterpret_cast<const double*>(p.ws + in.kw_off);
+  float2* t32 = reinterpret_cast<float2*>(p.ws + p.tbuf_off);
+  double2* t64 = reinterpret_cast<double2*>(p.ws + p.tbuf64_off);
+  double* epart = energy ? reinterpret_cast<double*>(p.ws + p.epart_off) : nullptr;
+  int nlb = 0;
+  bool ok;
+  p.prof.begin(FOCK_K_PLANE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_plane<double, N, false>(p, b, in, psi, parts, nullptr, t64)));
+  p.prof.end(FOCK_K_PLANE, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  p.prof.begin(FOCK_K_PENCIL, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_mixinv<N>(p, b, in, parts, qmap, t64, t32, vtab, occ, kw,
+                                                                       epart)));
+  p.prof.end(FOCK_K_PENCIL, p.stream);
+  if (!ok) return hipErrorInvalidValue;
+  if (energy) {
+    const hipError_t e = launch_sum_slot(p, static_cast<long long>(b.npairs) * nlb, b.eslot, b.mirror ? 2.0 : 1.0);
+    if (e != hipSuccess) return e;
+  }
+  p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
+  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc_all<float, N, double>(p, b, in, parts, t32, psi, occ, kw, out, gscale,
+                                                                        hscale, backward)));
   p.prof.end(FOCK_K_ACCUMULATE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1235,8 +1422,10 @@ size_t reg_lds_bytes(fock_precision prec, int L) {
   size_t r = 0;
 #define CASE(N)                                                                                \
   case N:                                                                                      \
-    r = prec == FOCK_C64 ? RegPolicy<float, N>::LDS                                            \
-                         : (prec == FOCK_MIXED ? MixedPolicy<N>::LDS : RegPolicy<double, N>::LDS); \
+    r = prec == FOCK_C64     ? RegPolicy<float, N>::LDS                                        \
+        : prec == FOCK_MIXED ? MixedPolicy<N>::LDS                                             \
+        : prec == FOCK_MIXED_INV ? MixInvPolicy<N>::LDS                                        \
+                                 : RegPolicy<double, N>::LDS;                                  \
     break;
   switch (L) { FOCK_REG_L(CASE) default: break; }
 #undef CASE
@@ -1247,6 +1436,7 @@ void prepare_reg_kernels(fock_precision prec, int lim) {
 #define CASE(N)                                     \
   if (prec == FOCK_C64) reg_lds_attr<float, N>(lim); \
   else if (prec == FOCK_MIXED) mixed_lds_attr<N>(lim); \
+  else if (prec == FOCK_MIXED_INV) { mixinv_lds_attr<N>(lim); reg_lds_attr<double, N>(lim); } \
   else reg_lds_attr<double, N>(lim);
   FOCK_REG_L(CASE)
 #undef CASE
@@ -1276,6 +1466,7 @@ void prepare_reg_dft_kernels(fock_precision prec, int lim) {
 hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi, const double* occ, void* out,
                                   const double* gscale, double hscale, bool backward, bool energy) {
   if (p.prec == FOCK_MIXED) return mixed_apply_t(p, b, psi, occ, out, gscale, hscale, backward, energy);
+  if (p.prec == FOCK_MIXED_INV) return mixinv_apply_t(p, b, psi, occ, out, gscale, hscale, backward, energy);
   return p.prec == FOCK_C128 ? reg_apply_t<double>(p, b, psi, occ, out, gscale, hscale, backward, energy)
                              : reg_apply_t<float>(p, b, psi, occ, out, gscale, hscale, backward, energy);
 }
@@ -1283,6 +1474,8 @@ hipError_t launch_reg_apply_batch(const Plan& p, const Batch& b, const void* psi
 
 hipError_t launch_reg_energy_batch(const Plan& p, const Batch& b, const void* psi, const double* occ) {
   if (p.prec == FOCK_MIXED) return mixed_energy_t(p, b, psi, occ);
+  // FOCK_MIXED_INV: the energy takes the FP64 forward transforms (its FP64 pair buffer)
+  if (p.prec == FOCK_MIXED_INV) return reg_energy_t<double>(p, b, psi, occ, p.tbuf64_off);
   return p.prec == FOCK_C128 ? reg_energy_t<double>(p, b, psi, occ) : reg_energy_t<float>(p, b, psi, occ);
 }
 

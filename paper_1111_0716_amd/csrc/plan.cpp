@@ -311,9 +311,10 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     // 416 against 606 ms per step), so it takes those instances.
     const bool sym_three_pass = !no_sym && !use_rounds && fused_rounds_supported(prec, in.grid) && full_kset(in) &&
                                 reg_supported(prec, in.grid) && !no_reg;
-    in.fused = prec != FOCK_MIXED && fused_supported(prec, in.grid) && !no_fused && !sym_three_pass;
+    const bool mixed = prec == FOCK_MIXED || prec == FOCK_MIXED_INV;
+    in.fused = !mixed && fused_supported(prec, in.grid) && !no_fused && !sym_three_pass;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
-    if (prec == FOCK_MIXED && !in.reg)
+    if (mixed && !in.reg)
       return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 36, 40, 48, 50, 54, 60, 64, 72}");
   }
 
@@ -543,7 +544,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   p->const_bytes = off;
   // ---- scratch ----
   p->tbuf_off = off;
-  if (prec == FOCK_MIXED) {
+  if (prec == FOCK_MIXED || prec == FOCK_MIXED_INV) {
     // FP32 pair buffer (plane pass out, pencil in), then the FP64 one
     p->tbuf64_off = align_up(off + max_pairs_elems * 8);
     p->tbuf_bytes = p->tbuf64_off - off + max_pairs_elems * 16;

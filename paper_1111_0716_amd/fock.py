@@ -20,8 +20,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("FOCK_LIBRARY") or os.path.join(HERE, "libfock.so")
 
 FOCK_OK, FOCK_ERR_ARG, FOCK_ERR_UNSUPPORTED, FOCK_ERR_NOMEM, FOCK_ERR_DEVICE, FOCK_ERR_STATE = range(6)
-FOCK_C128, FOCK_C64, FOCK_MIXED = 0, 1, 2
-PRECISIONS = {"c128": FOCK_C128, "c64": FOCK_C64, "mixed": FOCK_MIXED}
+FOCK_C128, FOCK_C64, FOCK_MIXED, FOCK_MIXED_INV = 0, 1, 2, 3
+PRECISIONS = {"c128": FOCK_C128, "c64": FOCK_C64, "mixed": FOCK_MIXED, "mixed_inv": FOCK_MIXED_INV}
 STATIC_WORKSPACE_BYTES = 64 << 20  # FOCK_STATIC_WORKSPACE_BYTES of fock.h
 
 EXPORTED = ["fock_plan", "fock_plan_tuned", "fock_workspace_size", "fock_set_workspace", "fock_set_stream", "fock_apply",

@@ -158,15 +158,16 @@ def test_mixed_precision_plans_need_register_line_grids():
         d = fock.make_desc(inputs.cubic_lattice(10.0), grid, np.zeros((1, 3)), nbands=2, keep=keep)
         arr = (fock.FockDesc * 1)(d)
         h = ctypes.c_void_p()
-        assert L.fock_plan(arr, 1, fock.FOCK_MIXED, None, ctypes.byref(h)) == want, grid
-        if want == fock.FOCK_OK:
-            size = ctypes.c_size_t()
-            assert L.fock_workspace_size(h, ctypes.byref(size)) == fock.FOCK_OK
-            L.fock_destroy(h)
+        for prec in (fock.FOCK_MIXED, fock.FOCK_MIXED_INV):
+            assert L.fock_plan(arr, 1, prec, None, ctypes.byref(h)) == want, (grid, prec)
+            if want == fock.FOCK_OK:
+                size = ctypes.c_size_t()
+                assert L.fock_workspace_size(h, ctypes.byref(size)) == fock.FOCK_OK
+                L.fock_destroy(h)
     d = fock.make_desc(inputs.cubic_lattice(10.0), (8, 8, 8), np.zeros((1, 3)), nbands=2, keep=keep)
     arr = (fock.FockDesc * 1)(d)
     h = ctypes.c_void_p()
-    assert L.fock_plan(arr, 1, 3, None, ctypes.byref(h)) == fock.FOCK_ERR_ARG
+    assert L.fock_plan(arr, 1, 4, None, ctypes.byref(h)) == fock.FOCK_ERR_ARG
 
 
 def test_static_workspace_limit_and_checks():

@@ -373,6 +373,51 @@ def test_mixed_precision_matches_oracle(grid, kmesh, nb, device):
     assert np.max(np.abs(g["vmat"] - mref)) <= TOL["c64"]["v"] * np.max(np.abs(mref))
 
 
+@pytest.mark.parametrize("grid,kmesh,nb", [((24, 24, 24), (2, 1, 1), 3), ((32, 32, 32), (1, 2, 1), 2),
+                                           ((40, 40, 40), (1, 1, 1), 2), ((64, 64, 64), (1, 1, 1), 1),
+                                           ((72, 72, 72), (1, 1, 1), 1), ((32, 72, 72), (1, 1, 1), 1),
+                                           ((72, 24, 24), (2, 1, 1), 2), ((60, 36, 36), (1, 1, 1), 2),
+                                           ((50, 54, 54), (1, 1, 1), 1)])
+def test_mixed_inv_precision_matches_oracle(grid, kmesh, nb, device):
+    """The other mixed policy: FP64 co-densities, forward transforms, kernel
+    multiply and energies, FP32 inverse transforms and accumulate into FP64
+    outputs; complex128 in and out, held to the FP32 tolerances, with E_x
+    from the FP64 spectrum."""
+    log(f"mixed_inv grid={grid} kmesh={kmesh} nb={nb}")
+    inst = inputs.small_instance(grid=grid, kmesh=kmesh, nbands=nb, seed=(214, grid[0]), full_grid=grid[0] == 32)
+    g = run_gpu(inst, "mixed_inv", device, vmat=True)
+    o = Oracle.from_instance(inst)
+    vref, eref = o.apply(inst.psi, inst.occ)
+    ev = band_err(g["vx"], vref)
+    ee = abs(g["ex"] - eref) / abs(eref)
+    log(f"  V_x err {ev:.3e}  E_x err {ee:.3e}")
+    assert ev <= TOL["c64"]["v"]
+    assert ee <= 1e-12  # fock_energy runs on the FP64 transforms
+    mref = o.overlap(inst.psi, vref)
+    assert np.max(np.abs(g["vmat"] - mref)) <= TOL["c64"]["v"] * np.max(np.abs(mref))
+    plan, psi, occ = g["plan"], g["psi"], g["occ"]
+    (v2,), _, ex2 = plan.fock_apply_energy([psi], [occ])
+    import torch
+
+    torch.cuda.synchronize()
+    assert np.array_equal(v2.cpu().numpy(), g["vx"])
+    assert abs(float(ex2.item()) - eref) <= 1e-12 * abs(eref)  # pair energies in FP64 in the apply too
+
+
+def test_mixed_inv_precision_backward(device):
+    import torch
+
+    inst = inputs.small_instance(grid=(24, 32, 32), kmesh=(2, 1, 1), nbands=3, seed=(215, 0), full_grid=True)
+    g = run_gpu(inst, "mixed_inv", device)
+    plan, psi, occ = g["plan"], g["psi"], g["occ"]
+    o = Oracle.from_instance(inst)
+    gref = o.gradient(inst.psi, inst.occ)
+    gex = torch.full((1,), 0.5, dtype=torch.float64, device=device)
+    (gg,) = plan.fock_energy_backward([psi], [occ], gex, 2.0 * o.dv)
+    torch.cuda.synchronize()
+    assert band_err(gg.cpu().numpy(), 0.5 * gref) <= TOL["c64"]["v"]
+
+
 def test_mixed_precision_backward(device):
     import torch
 

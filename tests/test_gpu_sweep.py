@@ -22,7 +22,8 @@ pytestmark = pytest.mark.gpu
 SMOOTH = [5, 6, 8, 9, 10, 12, 15, 16, 18, 20, 24, 25, 27, 30, 32, 36, 40, 45]
 REG = [24, 32, 36, 40, 48, 50, 54, 60, 64, 72]
 KMESHES = [(1, 1, 1), (2, 1, 1), (1, 2, 1), (1, 1, 2), (2, 2, 1)]
-TOL = {"c128": dict(e=1e-12, v=1e-12), "c64": dict(e=1e-6, v=1e-5), "mixed": dict(e=1e-6, v=1e-5)}
+TOL = {"c128": dict(e=1e-12, v=1e-12), "c64": dict(e=1e-6, v=1e-5), "mixed": dict(e=1e-6, v=1e-5),
+       "mixed_inv": dict(e=1e-6, v=1e-5)}
 # oracle budget per case: ordered pairs x N x (N1 + N2 + N3), the direct DFT's work
 BUDGET = 2e10
 NCASES = 64
@@ -47,7 +48,7 @@ def draw(i):
     else:            # larger smooth shapes
         grid = tuple(int(x) for x in rng.choice(SMOOTH[8:], 3))
     reg = grid[1] == grid[2] and grid[0] in REG and grid[1] in REG
-    precs = ["c64", "c128"] + (["mixed"] if reg else [])
+    precs = ["c64", "c128"] + (["mixed", "mixed_inv"] if reg else [])
     prec = precs[int(rng.integers(len(precs)))]
     n = int(np.prod(grid))
     kmesh = KMESHES[int(rng.integers(len(KMESHES)))]
