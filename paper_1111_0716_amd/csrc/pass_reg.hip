@@ -54,6 +54,8 @@ struct RegShape {
   // operand batches: larger where the kernel has a whole SIMD's registers
   static constexpr int PLANE_B = kRegB;
   static constexpr int ACC_B = (WPE_ACC == 1 && sizeof(T) == 4) ? 16 : kRegB;
+  // 128-byte lines of a workgroup's planes of one pair, per thread
+  static constexpr int PF_ACC = (PL * L * L * static_cast<int>(sizeof(C)) / 128 + NTP - 1) / NTP;
 };
 
 
@@ -395,7 +397,32 @@ __device__ __forceinline__ void acc_source(bool mirror, int j, int blk, int o0, 
   }
 }
 
-template <typename T, int L, typename TI = T>
+// Pull a byte range into L2 ahead of its use: one dword of every 128-byte
+// line is loaded into v[k].  Past the range the range's first line is
+// loaded again, so that every lane issues every load (no branch, so the
+// compiler counts the loads in flight exactly).  The caller consumes v with
+// prefetch_done where it may wait for them.
+template <int NT, int PER>
+__device__ __forceinline__ void prefetch_l2(const void* base, unsigned bytes, int t, unsigned (&v)[PER]) {
+  const unsigned* b = static_cast<const unsigned*>(base);
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const unsigned off = static_cast<unsigned>(t + k * NT) * 128u;
+    v[k] = b[(off < bytes ? off : 0u) / 4u];
+  }
+  reg_fence();  // issued here, not moved to their use
+}
+
+template <int PER>
+__device__ __forceinline__ void prefetch_done(const unsigned (&v)[PER]) {
+#pragma unroll
+  for (int k = 0; k < PER; ++k) asm volatile("" ::"v"(v[k]));
+}
+
+// PF: while a partner is transformed, the next partner's pair-buffer rows of
+// the workgroup's planes are pulled into L2 (prefetch_l2), so that their
+// loads wait on L2 rather than on HBM
+template <typename T, int L, typename TI = T, bool PF = false>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) void k_acc_reg(
     int n1, int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<TI>::t* __restrict__ psi,
@@ -434,6 +461,19 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
 #pragma unroll
       for (int c3 = 0; c3 < L; ++c3) x[c3] = C{T(0), T(0)};
     }
+    unsigned pfv[Sh::PF_ACC];
+    if constexpr (PF) {
+      // the next partner's rows (the last partner: its own again), behind
+      // this partner's: the transforms wait only for the latter
+      int sb1;
+      size_t pair1;
+      bool cj1;
+      acc_source(mirror, p + 1 < nsrc ? p + 1 : p, o, o0, nP, tri, nbands, parts, &sb1, &pair1, &cj1);
+      const int j10 = static_cast<int>(blockIdx.x) * Sh::PL;
+      const int planes = min(Sh::PL, n1 - j10);
+      prefetch_l2<Sh::NTP, Sh::PF_ACC>(tbuf + (pair1 * n1 + j10) * LL, static_cast<unsigned>(planes * LL * sizeof(C)), t,
+                                       pfv);
+    }
     reg_fft<C, L, +1>(x);                   // inverse axis 3: x[j3] at (j1, c2 = col)
     transpose_plane<C, T, L>(x, sp, col);   // column (j1, j3 = col)
     reg_fft<C, L, +1>(x);                   // inverse axis 2: x[j2]
@@ -462,6 +502,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
         }
       }
     }
+    if constexpr (PF) prefetch_done(pfv);
   }
   if (!valid) return;  // no barrier after this point
   const int okn = mirror ? parts[o].x * nbands + parts[o].y : o0 + o;
@@ -960,6 +1001,11 @@ struct RegPolicy {
   static constexpr bool SPLIT_PLANE = !FP32 && L >= 36;
   static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 36;
   static constexpr bool SPLIT_ACC = FP32 ? (L >= 54 && L <= 64) : L >= 36;
+  // L2 prefetch of the next partner in the one-lane accumulate: measured
+  // where that kernel runs one wave per SIMD at FP32 72 points (beta boron
+  // 8.71 against 8.89 s per step); at 32 points, two waves per SIMD, it
+  // costs (428 against 382 ms per step at alpha boron)
+  static constexpr bool ACC_PREFETCH = FP32 && L == 72;
   static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;
@@ -1064,7 +1110,8 @@ void launch_acc_kernel(const Plan& p, const Batch& b, const Instance& in, const 
                        occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
   } else {
     using Sh = RegShape<T, L>;
-    hipLaunchKernelGGL((k_acc_reg<T, L, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS,
+    constexpr bool PF = sizeof(TI) == sizeof(T) && RegPolicy<T, L>::ACC_PREFETCH;
+    hipLaunchKernelGGL((k_acc_reg<T, L, TI, PF>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS,
                        p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi),
                        occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
   }
@@ -1094,7 +1141,7 @@ void reg_lds_attr(int lim) {
   if constexpr (Po::SPLIT_ACC)
     fs[2] = reinterpret_cast<const void*>(&k_acc_split<T, L>);
   else
-    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L>);
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<T, L, T, Po::ACC_PREFETCH>);
   fs[3] = fs[2];
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
@@ -1132,7 +1179,7 @@ void mixed_lds_attr(int lim) {
   if constexpr (Acc::SPLIT_ACC)
     fs[2] = reinterpret_cast<const void*>(&k_acc_split<double, L>);
   else
-    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L>);
+    fs[2] = reinterpret_cast<const void*>(&k_acc_reg<double, L, double, Acc::ACC_PREFETCH>);
   fs[3] = fs[2];
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
