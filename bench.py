@@ -389,6 +389,10 @@ def host_info():
         info["torch_hip"] = torch.version.hip
         if torch.cuda.is_available():
             info["gpu"] = torch.cuda.get_device_name(0)
+            props = torch.cuda.get_device_properties(0)
+            info["gpu_arch"] = getattr(props, "gcnArchName", None)
+            info["gpu_cus"] = props.multi_processor_count
+            info["gpu_mem_gib"] = round(props.total_memory / 2**30, 1)
     except ImportError:
         pass
     return info
