@@ -47,6 +47,9 @@ CASES = [
     ((24, 40, 40), (2, 1, 1), 2, "c128", 2),   # two-lane accumulate (FP64 >= 36)
     ((24, 32, 32), (2, 1, 1), 3, "mixed", 1),  # FP64 accumulate of the mixed path
     ((72, 24, 24), (1, 1, 2), 3, "c64", 2),    # pencil of length 72 (two-lane), 3 planes per group
+    # plane side 72 (FP32, one-lane accumulate with the L2 prefetch)
+    ((24, 72, 72), (2, 1, 1), 3, "c64", 4),    # 4 pairs -> blocks 2, 2, 2
+    ((24, 72, 72), (1, 1, 1), 5, "c64", 2),    # 2 pairs -> blocks of one orbital
 ]
 
 
