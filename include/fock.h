@@ -129,7 +129,8 @@ fock_status fock_plan(const fock_desc* descs, int32_t n_inst, fock_precision pre
  *                   (one workgroup per pair, rounds of pairwise disjoint
  *                   pairs, one launch per round; needs a k-pair list closed
  *                   under swapping); 0: one workgroup per output
- * Defaults: acc_workgroups 2048, tbuf_mb 4096 (or $FOCK_TBUF_MB), fused_split
+ * Defaults: acc_workgroups 2048, tbuf_mb 4096, 8192 for FOCK_C128 (or
+ * $FOCK_TBUF_MB), fused_split
  * chosen to fill the compute units evenly, pair symmetry on (off with
  * $FOCK_NO_PAIR_SYMMETRY=1), fused_rounds off (on with $FOCK_FUSED_ROUNDS=1). */
 typedef struct {

@@ -1001,11 +1001,12 @@ struct RegPolicy {
   static constexpr bool SPLIT_PLANE = !FP32 && L >= 36;
   static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 36;
   static constexpr bool SPLIT_ACC = FP32 ? (L >= 54 && L <= 64) : L >= 36;
-  // L2 prefetch of the next partner in the one-lane accumulate: measured
-  // where that kernel runs one wave per SIMD at FP32 72 points (beta boron
-  // 8.71 against 8.89 s per step); at 32 points, two waves per SIMD, it
-  // costs (428 against 382 ms per step at alpha boron)
-  static constexpr bool ACC_PREFETCH = FP32 && L == 72;
+  // L2 prefetch of the next partner in the one-lane accumulate, measured
+  // where that kernel runs one wave per SIMD: FP32 72 points (beta boron
+  // 8.71 against 8.89 s per step) and FP64 32 points (alpha boron
+  // accumulate 566 against 586 ms per step); at FP32 32 points, two waves per
+  // SIMD, it costs (428 against 382 ms per step at alpha boron)
+  static constexpr bool ACC_PREFETCH = FP32 ? L == 72 : L == 32;
   static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;

@@ -319,7 +319,12 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   }
 
   // ---- batch shapes ----
-  const size_t tbuf_target = (tn.tbuf_mb > 0 ? static_cast<size_t>(tn.tbuf_mb) : env_mb("FOCK_TBUF_MB", 4096)) << 20;
+  // pair-buffer budget: 4 GiB, 8 GiB in FP64, whose pairs are twice the
+  // bytes (the same block shapes; alpha boron FP64 1.02 s per step against
+  // 1.06 s at 4 GiB)
+  const size_t tbuf_default = prec == FOCK_C128 ? 8192 : 4096;
+  const size_t tbuf_target =
+      (tn.tbuf_mb > 0 ? static_cast<size_t>(tn.tbuf_mb) : env_mb("FOCK_TBUF_MB", tbuf_default)) << 20;
   const int acc_wgs = tn.acc_workgroups > 0 ? tn.acc_workgroups : 2048;
 
   // ---- workspace layout: constant prefix ----
