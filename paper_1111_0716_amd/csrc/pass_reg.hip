@@ -1000,13 +1000,15 @@ struct RegPolicy {
   static constexpr bool FP32 = sizeof(T) == 4;
   static constexpr bool SPLIT_PLANE = !FP32 && L >= 36;
   static constexpr bool SPLIT_PENCIL = FP32 ? L >= 64 : L >= 36;
-  static constexpr bool SPLIT_ACC = FP32 ? (L >= 54 && L <= 64) : L >= 36;
-  // L2 prefetch of the next partner in the one-lane accumulate, measured
-  // where that kernel runs one wave per SIMD: FP32 72 points (beta boron
-  // 8.71 against 8.89 s per step) and FP64 32 points (alpha boron
-  // accumulate 566 against 586 ms per step); at FP32 32 points, two waves per
-  // SIMD, it costs (428 against 382 ms per step at alpha boron)
-  static constexpr bool ACC_PREFETCH = FP32 ? L == 72 : L == 32;
+  // FP64 32 points over lane pairs too: alpha boron FP64 accumulate 462
+  // against 518 ms per step for one lane (one-wave workgroups with the L2
+  // prefetch, 586 ms as four-wave ones without)
+  static constexpr bool SPLIT_ACC = FP32 ? (L >= 54 && L <= 64) : L >= 32;
+  // L2 prefetch of the next partner in the one-lane accumulate, where that
+  // kernel runs one wave per SIMD: FP32 72 points (beta boron 8.71 against
+  // 8.89 s per step); at FP32 32 points, two waves per SIMD, it costs (428
+  // against 382 ms per step at alpha boron)
+  static constexpr bool ACC_PREFETCH = FP32 && L == 72;
   static constexpr int PLANE_LDS = SPLIT_PLANE ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int ACC_LDS = SPLIT_ACC ? SplitShape<T, L>::LDS : RegShape<T, L>::LDS;
   static constexpr int LDS = PLANE_LDS > ACC_LDS ? PLANE_LDS : ACC_LDS;
