@@ -83,6 +83,7 @@ struct Instance {
   bool symmetric = true;                     // (k, k') listed iff (k', k) listed
   bool fused = false;                        // whole-pair path (cubic grid that fits one CU)
   bool reg = false;                          // three-pass path with register-line kernels (N1 x L x L)
+  bool slab = false;                         // cubic FP32 register-line path with the slab pencil (pair buffer [j1][c2][c3])
   int rounds = -1;                           // whole-pair path by unordered pairs: its FusedRounds
   int nbands;
   int64_t band_stride;
@@ -220,6 +221,9 @@ int fused_threads(fock_precision prec, int L);
 size_t overlap_scratch_bytes(const Instance& in);
 void prepare_fused_kernels(fock_precision prec, int lim);
 bool reg_supported(fock_precision prec, const int grid[3]);
+// grids where the register-line path can run its pencil pass over slabs of
+// fixed c2 (and the accumulate over independent lines)
+bool reg_slab_supported(fock_precision prec, const int grid[3]);
 size_t reg_lds_bytes(fock_precision prec, int L);
 void prepare_reg_kernels(fock_precision prec, int lim);
 // energy: the pencil pass also writes the batch's weighted pair energies to

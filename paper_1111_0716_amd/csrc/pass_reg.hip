@@ -221,12 +221,37 @@ __device__ __forceinline__ void transpose_plane(C* x, T* sp, int col) {
   for (int i = 0; i < L; ++i) x[i].y = sp[col * LP + i];
 }
 
+// The line through LDS and back in place: each thread its own slots, after
+// one barrier for earlier readers of sp.  The values do not change; after the
+// last transform of the FP32 72-point plane pass it lets the compiler
+// allocate that kernel without scratch (205 registers, where it otherwise
+// keeps about 40 values of the second transform in 156 bytes of scratch per
+// lane at the 256 registers of two waves per SIMD).
+template <typename C, typename T, int L>
+__device__ __forceinline__ void lds_round_trip(C* x, T* sp, int col) {
+  constexpr int LP = L + 1;
+  __syncthreads();  // earlier readers of sp are done
+#pragma unroll
+  for (int i = 0; i < L; ++i) sp[i * LP + col] = x[i].x;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < L; ++i) x[i].x = sp[i * LP + col];
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < L; ++i) sp[i * LP + col] = x[i].y;
+  asm volatile("" ::: "memory");
+#pragma unroll
+  for (int i = 0; i < L; ++i) x[i].y = sp[i * LP + col];
+}
+
 // ---------------------------------------------------------------------------
 // plane pass: rho = conj(u_m) u_n, FFT along axes 2 and 3, T[j1][c3][c2]
 // ---------------------------------------------------------------------------
 // (orbitals wider than the transform, FOCK_MIXED: one wave per SIMD, so the
 // wide operands fit beside the line without spilling)
-template <typename T, int L, bool EXPLICIT, typename TI = T>
+// SLAB: the pair buffer leaves as [j1][c2][c3] (one more transpose) for the
+// slab pencil; otherwise as [j1][c3][c2]
+template <typename T, int L, bool EXPLICIT, typename TI = T, bool SLAB = false>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? RegShape<T, L>::WPE_PLANE : 1)) void k_plane_reg(
     int n1, int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP, int tri,
     const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
@@ -262,6 +287,10 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? R
   reg_fft<C, L, -1>(x);  // axis 2: x[c2] at (j1, c2, j3 = col)
   transpose_plane<C, T, L>(x, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col);  // now c2 = col
   reg_fft<C, L, -1>(x);  // axis 3: x[c3]
+  if constexpr (SLAB)
+    transpose_plane<C, T, L>(x, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col);  // x[c2], c3 = col
+  else if constexpr (sizeof(TI) == sizeof(T) && sizeof(T) == 4 && L == 72)
+    lds_round_trip<C, T, L>(x, reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP, col);
   if (valid) {
     if constexpr (sizeof(TI) != sizeof(T)) {
       // wide orbitals: addresses formed at the stores (the form with the
@@ -726,6 +755,77 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_ap
   }
 }
 
+// ---------------------------------------------------------------------------
+// slab pencil (cubic L^3, pair buffer [j1][c2][c3] from the SLAB plane pass):
+// one slab of fixed c2 per L * 2 threads, its lines (c2, c3 = col) along axis
+// 1 over lane pairs: FFT_1, x v_q/N (pair energies with EN), IFFT_1; a
+// transpose to lines along axis 3 for fixed j1 = col, IFFT_3; a transpose
+// back, so that the pair buffer leaves as [j1][c2][j3], read by the line
+// accumulate along axis 2.  The table is in grid order [c1][c2][c3].
+// ---------------------------------------------------------------------------
+template <typename T, int L, bool EN>
+__global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LINE)) void k_pencil_slab(
+    int nbands, int nk, int o0, int nP, int tri, const int2* __restrict__ parts, const int* __restrict__ qmap,
+    typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab, const double* __restrict__ occ,
+    const double* __restrict__ kw, double* __restrict__ epart) {
+  using C = typename cx<T>::t;
+  using Sh = SplitShape<T, L>;
+  constexpr int LL = L * L, LH = Sh::LH;
+  extern __shared__ unsigned char smem_raw[];
+  const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
+  const int c2 = blockIdx.x * Sh::PL + pl;
+  const bool valid = c2 < L;
+  const int pi = blockIdx.y;
+  int o, p;
+  batch_pair(pi, nP, tri, &o, &p);
+  const int ok = (o0 + o) / nbands;
+  const int2 r = parts[p];
+  const int q = qmap[ok * nk + r.x];
+  T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
+  C* base = tbuf + static_cast<size_t>(pi) * LL * L;
+  C y[LH];
+  double e = 0.0;
+  if (valid) {
+    const unsigned lo = (static_cast<unsigned>(h) * LL + static_cast<unsigned>(c2) * L + col) * sizeof(C);
+#pragma unroll
+    for (int m = 0; m < LH; ++m) y[m] = *lane_at(base + static_cast<size_t>(2 * m) * LL, lo);  // j1 = 2m + h
+    split_fft_fwd<C, L>(y, h);  // y[k] at c1 = h L/2 + k
+    mul_table_line_u<C, T, LH, EN>(y, vtab + static_cast<size_t>(q) * LL * L,
+                                   opaque((static_cast<unsigned>(h) * LH * LL + static_cast<unsigned>(c2) * L + col) *
+                                          sizeof(T)),
+                                   LL, &e);
+    split_fft_inv<C, L>(y, h);  // y[m] at j1 = 2m + h
+  } else {
+#pragma unroll
+    for (int m = 0; m < LH; ++m) y[m] = C{T(0), T(0)};
+  }
+  transpose_split<C, T, L, true>(y, sp, col, h);  // line j1 = col: y[k] at c3 = h L/2 + k
+  split_fft_inv<C, L>(y, h);                      // y[m] at j3 = 2m + h
+  transpose_split<C, T, L, true>(y, sp, col, h);  // line j3 = col: y[k] at j1 = h L/2 + k
+  if (valid) {
+    const unsigned so = opaque((static_cast<unsigned>(c2) * L + col) * sizeof(C));
+#pragma unroll
+    for (int k = 0; k < LH; ++k) *lane_at(base + static_cast<size_t>(h * LH + k) * LL, so) = y[k];
+  }
+  if constexpr (EN) {
+    // block sum in a fixed order (the block's last wave is partly empty):
+    // the first wave adds the threads' partials with stride 64, then across
+    // its lanes
+    __shared__ double red[Sh::NTP];
+    red[t] = e;
+    __syncthreads();
+    if (t < 64) {
+      double sum = 0.0;
+      for (int i = t; i < Sh::NTP; i += 64) sum += red[i];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      if (t == 0)
+        epart[static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x] =
+            (tri && o != p ? 2.0 : 1.0) * kw[ok] * occ[o0 + o] * kw[r.x] * occ[r.x * nbands + r.y] * sum;
+    }
+  }
+}
+
 template <typename T, int L, typename TV = T>
 __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_energy_split(
     int ll, const PairRef* __restrict__ pairs, const typename cx<T>::t* __restrict__ tbuf, const TV* __restrict__ vtab,
@@ -863,6 +963,86 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
 #pragma unroll
       for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cscale(acc[m], ft);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// line accumulate (pair buffer [j1][c2][j3] from the slab pencil): each thread
+// one line (j1, j3) along axis 2, for every partner IFFT_2 and the partner's
+// orbital along j2 at (j1, j3).  No transpose, so no LDS and no barrier, and
+// the lines need not fill whole planes: every lane of a workgroup works.
+// Rows and partners as in k_acc_reg.
+// ---------------------------------------------------------------------------
+template <typename T, int L>
+__global__ __launch_bounds__(256, 1) void k_acc_line(
+    int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
+    const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
+    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    int first_mirror, const double* __restrict__ gscale, double hscale, int backward) {
+  using C = typename cx<T>::t;
+  constexpr int LL = L * L;
+  constexpr int B = batch_of(L, 16);
+  constexpr int NB = L / B;
+  const int l = static_cast<int>(blockIdx.x) * 256 + static_cast<int>(threadIdx.x);  // line (j1, j3)
+  if (l >= LL) return;  // no barrier in this kernel
+  const int row = static_cast<int>(blockIdx.y);
+  const bool mirror = row >= nO;
+  const int o = mirror ? row - nO : row;
+  const int nsrc = mirror ? nO : nP;
+  const int j1 = l / L, j3 = l - (l / L) * L;
+  const size_t eoff = static_cast<size_t>(j1) * LL + j3;  // element (j1, 0, j3); axis 2 has stride L
+  C acc[L];
+#pragma unroll
+  for (int j2 = 0; j2 < L; ++j2) acc[j2] = C{T(0), T(0)};
+  for (int p = 0; p < nsrc; ++p) {
+    int sb;
+    size_t pair;
+    bool cj;
+    acc_source(mirror, p, o, o0, nP, tri, nbands, parts, &sb, &pair, &cj);
+    const C* src = tbuf + pair * LL * L + eoff;
+    C x[L];
+#pragma unroll
+    for (int c2 = 0; c2 < L; ++c2) x[c2] = src[c2 * L];
+    reg_fft<C, L, +1>(x);  // inverse axis 2: x[j2] at (j1, j3)
+    if (cj) {
+#pragma unroll
+      for (int j2 = 0; j2 < L; ++j2) x[j2].y = -x[j2].y;
+    }
+    const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
+    const C* um = psi + static_cast<size_t>(sb) * bs + eoff;
+    C mb[2][B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) mb[0][j] = um[j * L];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      if (n + 1 < NB) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = um[((n + 1) * B + j) * L];
+      }
+      reg_fence();
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const C w = cmul(mb[n & 1][j], x[n * B + j]);
+        acc[n * B + j].x += coef * w.x;
+        acc[n * B + j].y += coef * w.y;
+      }
+    }
+  }
+  const int okn = mirror ? parts[o].x * nbands + parts[o].y : o0 + o;
+  double f = hscale;
+  if (gscale) f *= gscale[0];
+  if (backward) f *= kw[okn / nbands] * occ[okn];
+  const T ft = static_cast<T>(f);
+  C* dst = out + static_cast<size_t>(okn) * bs + eoff;
+  if (!(mirror ? first_mirror : first)) {
+    C old[L];  // loaded before the first store (see k_acc_reg)
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) old[j2] = dst[j2 * L];
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cadd(old[j2], cscale(acc[j2], ft));
+  } else {
+#pragma unroll
+    for (int j2 = 0; j2 < L; ++j2) dst[j2 * L] = cscale(acc[j2], ft);
   }
 }
 
@@ -1021,6 +1201,12 @@ namespace {
 // compiled for the line length N1 and takes the line count L^2 at run time.
 // Each pass is dispatched on its own length.
 
+// lengths compiled with the slab pencil and the line accumulate
+template <typename T, int L>
+constexpr bool slab_len() {
+  return sizeof(T) == 4 && L == 72;
+}
+
 template <typename T, int L, bool EXPLICIT, typename TI = T>
 void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void* psi, const int2* parts,
                   const PairRef* pairs, typename cx<T>::t* tbuf) {
@@ -1040,8 +1226,55 @@ void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void*
                        Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, tri, parts, pairs, tbuf);
   } else {
     using Sh = RegShape<T, L>;
+    if constexpr (slab_len<T, L>()) {
+      if (in.slab) {  // pair buffer [j1][c2][c3] for the slab pencil
+        hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, T, true>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs),
+                           dim3(Sh::NTP), Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP,
+                           tri, parts, pairs, tbuf);
+        return;
+      }
+    }
     hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
                        Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, tri, parts, pairs, tbuf);
+  }
+}
+
+// the slab pencil of an apply batch (cubic grids); epart not null: the
+// energy variant; returns the slabs' workgroups per pair (0: not compiled)
+template <typename T, int L>
+int launch_pencil_slab(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
+                       typename cx<T>::t* tbuf, const T* vtab, const double* occ, const double* kw, double* epart) {
+  if constexpr (slab_len<T, L>()) {
+    using Sh = SplitShape<T, L>;
+    const int nlb = (L + Sh::PL - 1) / Sh::PL;
+    if (epart)
+      hipLaunchKernelGGL((k_pencil_slab<T, L, true>), dim3(nlb, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
+                         in.nbands, in.nk, b.o0, b.nP, b.tri, parts, qmap, tbuf, vtab, occ, kw, epart);
+    else
+      hipLaunchKernelGGL((k_pencil_slab<T, L, false>), dim3(nlb, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,
+                         in.nbands, in.nk, b.o0, b.nP, b.tri, parts, qmap, tbuf, vtab, occ, kw, epart);
+    return nlb;
+  } else {
+    return 0;
+  }
+}
+
+// the line accumulate of an apply batch: its outputs and, for a batch of two
+// blocks, its partners in the same launch (false: not compiled)
+template <typename T, int L>
+bool launch_acc_line(const Plan& p, const Batch& b, const Instance& in, const int2* parts,
+                     const typename cx<T>::t* tbuf, const void* psi, const double* occ, const double* kw, void* out,
+                     const double* gscale, double hscale, bool backward) {
+  if constexpr (slab_len<T, L>()) {
+    using C = typename cx<T>::t;
+    const int rows = b.nO + (b.mirror ? b.nP : 0);
+    hipLaunchKernelGGL((k_acc_line<T, L>), dim3((L * L + 255) / 256, rows), dim3(256), 0, p.stream, in.nbands,
+                       static_cast<long long>(in.band_stride), b.o0, b.nO, b.nP, b.tri, parts, tbuf,
+                       static_cast<const C*>(psi), occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale,
+                       hscale, backward ? 1 : 0);
+    return true;
+  } else {
+    return false;
   }
 }
 
@@ -1269,8 +1502,13 @@ hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const dou
   p.prof.end(FOCK_K_PLANE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   p.prof.begin(FOCK_K_PENCIL, p.stream);
-  ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_apply<T, N>(p, b, in, parts, qmap, tbuf, vtab, occ, kw,
-                                                                       epart)));
+  if (in.slab)
+    ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_slab<T, N>(p, b, in, parts, qmap, tbuf, vtab, occ, kw,
+                                                                        epart))) &&
+         nlb > 0;
+  else
+    ok = FOCK_REG_DISPATCH(in.grid[0], (nlb = launch_pencil_apply<T, N>(p, b, in, parts, qmap, tbuf, vtab, occ, kw,
+                                                                         epart)));
   p.prof.end(FOCK_K_PENCIL, p.stream);
   if (!ok) return hipErrorInvalidValue;
   if (energy) {
@@ -1278,8 +1516,15 @@ hipError_t reg_apply_t(const Plan& p, const Batch& b, const void* psi, const dou
     if (e != hipSuccess) return e;
   }
   p.prof.begin(FOCK_K_ACCUMULATE, p.stream);
-  ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc_all<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale, hscale,
-                                                            backward)));
+  if (in.slab) {
+    bool launched = false;
+    ok = FOCK_REG_DISPATCH(in.grid[1], (launched = launch_acc_line<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out,
+                                                                         gscale, hscale, backward))) &&
+         launched;
+  } else {
+    ok = FOCK_REG_DISPATCH(in.grid[1], (launch_acc_all<T, N>(p, b, in, parts, tbuf, psi, occ, kw, out, gscale,
+                                                              hscale, backward)));
+  }
   p.prof.end(FOCK_K_ACCUMULATE, p.stream);
   if (!ok) return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1462,6 +1707,10 @@ hipError_t reg_dft3_t(const Plan& p, int inst, int count, void* data, long long 
 }
 
 }  // namespace
+
+bool reg_slab_supported(fock_precision prec, const int grid[3]) {
+  return prec == FOCK_C64 && grid[0] == 72 && grid[1] == 72 && grid[2] == 72;
+}
 
 bool reg_supported(fock_precision prec, const int grid[3]) {
   (void)prec;

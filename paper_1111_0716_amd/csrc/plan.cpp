@@ -302,6 +302,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const bool no_reg = noreg && *noreg && *noreg != '0';
   const char* nosym = std::getenv("FOCK_NO_PAIR_SYMMETRY");
   const bool no_sym = tn.no_pair_symmetry != 0 || (nosym && *nosym && *nosym != '0');
+  const char* slab_env = std::getenv("FOCK_SLAB");
+  const bool use_slab = slab_env && *slab_env && *slab_env != '0';
   const char* rounds_env = std::getenv("FOCK_FUSED_ROUNDS");
   const bool use_rounds = tn.fused_rounds != 0 || (rounds_env && *rounds_env && *rounds_env != '0');
   for (auto& in : p->inst) {
@@ -314,6 +316,7 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     const bool mixed = prec == FOCK_MIXED || prec == FOCK_MIXED_INV;
     in.fused = !mixed && fused_supported(prec, in.grid) && !no_fused && !sym_three_pass;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
+    in.slab = in.reg && use_slab && reg_slab_supported(prec, in.grid);
     if (mixed && !in.reg)
       return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 36, 40, 48, 50, 54, 60, 64, 72}");
   }
@@ -637,9 +640,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
             for (int c3 = 0; c3 < L; ++c3)
               r[(static_cast<size_t>(c3) * L + c2) * L + c1] = t[(static_cast<size_t>(c1) * L + c2) * L + c3];
         t.swap(r);
-      } else if (in.reg) {
+      } else if (in.reg && !in.slab) {
         // register-line three-pass path reads the table as [c1][c3][c2]
-        // (grids N1 x L x L)
+        // (grids N1 x L x L; the slab pencil reads it in grid order)
         const int n1 = in.grid[0], L = in.grid[1];
         std::vector<double> r(t.size());
         for (int c1 = 0; c1 < n1; ++c1)
