@@ -757,22 +757,23 @@ __global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_LINE)) void k_pencil_ap
 
 // ---------------------------------------------------------------------------
 // slab pencil (cubic L^3, pair buffer [j1][c2][c3] from the SLAB plane pass):
-// one slab of fixed c2 per L * 2 threads, its lines (c2, c3 = col) along axis
-// 1 over lane pairs: FFT_1, x v_q/N (pair energies with EN), IFFT_1; a
+// one slab of fixed c2 per L threads, thread col = c3 holding the line
+// (c2, c3) along axis 1: FFT_1, x v_q/N (pair energies with EN), IFFT_1; a
 // transpose to lines along axis 3 for fixed j1 = col, IFFT_3; a transpose
-// back, so that the pair buffer leaves as [j1][c2][j3], read by the line
-// accumulate along axis 2.  The table is in grid order [c1][c2][c3].
+// back (the same LDS round as the plane pass), so that the pair buffer
+// leaves as [j1][c2][j3], read by the line accumulate along axis 2.  The
+// table is in grid order [c1][c2][c3].
 // ---------------------------------------------------------------------------
 template <typename T, int L, bool EN>
-__global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LINE)) void k_pencil_slab(
+__global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_PLANE)) void k_pencil_slab(
     int nbands, int nk, int o0, int nP, int tri, const int2* __restrict__ parts, const int* __restrict__ qmap,
     typename cx<T>::t* __restrict__ tbuf, const T* __restrict__ vtab, const double* __restrict__ occ,
     const double* __restrict__ kw, double* __restrict__ epart) {
   using C = typename cx<T>::t;
-  using Sh = SplitShape<T, L>;
-  constexpr int LL = L * L, LH = Sh::LH;
+  using Sh = RegShape<T, L>;
+  constexpr int LL = L * L;
   extern __shared__ unsigned char smem_raw[];
-  const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
+  const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
   const int c2 = blockIdx.x * Sh::PL + pl;
   const bool valid = c2 < L;
   const int pi = blockIdx.y;
@@ -783,32 +784,30 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_LIN
   const int q = qmap[ok * nk + r.x];
   T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
   C* base = tbuf + static_cast<size_t>(pi) * LL * L;
-  C y[LH];
+  C x[L];
   double e = 0.0;
   if (valid) {
-    const unsigned lo = (static_cast<unsigned>(h) * LL + static_cast<unsigned>(c2) * L + col) * sizeof(C);
+    const unsigned lo = (static_cast<unsigned>(c2) * L + col) * sizeof(C);
 #pragma unroll
-    for (int m = 0; m < LH; ++m) y[m] = *lane_at(base + static_cast<size_t>(2 * m) * LL, lo);  // j1 = 2m + h
-    split_fft_fwd<C, L>(y, h);  // y[k] at c1 = h L/2 + k
-    mul_table_line_u<C, T, LH, EN>(y, vtab + static_cast<size_t>(q) * LL * L,
-                                   opaque((static_cast<unsigned>(h) * LH * LL + static_cast<unsigned>(c2) * L + col) *
-                                          sizeof(T)),
-                                   LL, &e);
-    split_fft_inv<C, L>(y, h);  // y[m] at j1 = 2m + h
+    for (int j1 = 0; j1 < L; ++j1) x[j1] = *lane_at(base + static_cast<size_t>(j1) * LL, lo);
+    reg_fft<C, L, -1>(x);  // axis 1: x[c1] at (c2, c3 = col)
+    mul_table_line_u<C, T, L, EN>(x, vtab + static_cast<size_t>(q) * LL * L,
+                                  opaque((static_cast<unsigned>(c2) * L + col) * sizeof(T)), LL, &e);
+    reg_fft<C, L, +1>(x);  // x[j1]
   } else {
 #pragma unroll
-    for (int m = 0; m < LH; ++m) y[m] = C{T(0), T(0)};
+    for (int j1 = 0; j1 < L; ++j1) x[j1] = C{T(0), T(0)};
   }
-  transpose_split<C, T, L, true>(y, sp, col, h);  // line j1 = col: y[k] at c3 = h L/2 + k
-  split_fft_inv<C, L>(y, h);                      // y[m] at j3 = 2m + h
-  transpose_split<C, T, L, true>(y, sp, col, h);  // line j3 = col: y[k] at j1 = h L/2 + k
+  transpose_plane<C, T, L>(x, sp, col);  // line j1 = col: x[c3]
+  reg_fft<C, L, +1>(x);                  // x[j3]
+  transpose_plane<C, T, L>(x, sp, col);  // line j3 = col: x[j1]
   if (valid) {
     const unsigned so = opaque((static_cast<unsigned>(c2) * L + col) * sizeof(C));
 #pragma unroll
-    for (int k = 0; k < LH; ++k) *lane_at(base + static_cast<size_t>(h * LH + k) * LL, so) = y[k];
+    for (int j1 = 0; j1 < L; ++j1) *lane_at(base + static_cast<size_t>(j1) * LL, so) = x[j1];
   }
   if constexpr (EN) {
-    // block sum in a fixed order (the block's last wave is partly empty):
+    // block sum in a fixed order (the block's last wave may be partly empty):
     // the first wave adds the threads' partials with stride 64, then across
     // its lanes
     __shared__ double red[Sh::NTP];
@@ -1245,7 +1244,7 @@ template <typename T, int L>
 int launch_pencil_slab(const Plan& p, const Batch& b, const Instance& in, const int2* parts, const int* qmap,
                        typename cx<T>::t* tbuf, const T* vtab, const double* occ, const double* kw, double* epart) {
   if constexpr (slab_len<T, L>()) {
-    using Sh = SplitShape<T, L>;
+    using Sh = RegShape<T, L>;
     const int nlb = (L + Sh::PL - 1) / Sh::PL;
     if (epart)
       hipLaunchKernelGGL((k_pencil_slab<T, L, true>), dim3(nlb, b.npairs), dim3(Sh::NTP), Sh::LDS, p.stream,

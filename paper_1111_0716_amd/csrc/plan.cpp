@@ -302,8 +302,9 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const bool no_reg = noreg && *noreg && *noreg != '0';
   const char* nosym = std::getenv("FOCK_NO_PAIR_SYMMETRY");
   const bool no_sym = tn.no_pair_symmetry != 0 || (nosym && *nosym && *nosym != '0');
+  // FOCK_SLAB=0 keeps cubic grids on the plane-wise accumulate (measurement switch)
   const char* slab_env = std::getenv("FOCK_SLAB");
-  const bool use_slab = slab_env && *slab_env && *slab_env != '0';
+  const bool use_slab = !(slab_env && *slab_env == '0');
   const char* rounds_env = std::getenv("FOCK_FUSED_ROUNDS");
   const bool use_rounds = tn.fused_rounds != 0 || (rounds_env && *rounds_env && *rounds_env != '0');
   for (auto& in : p->inst) {

@@ -194,9 +194,10 @@ def test_pair_rounds_of_the_whole_pair_path_match_oracle(kmesh, nb, kpairs, devi
     ref.close()
 
 
-# cubic 72^3 FP32 with FOCK_SLAB=1: the plane pass leaves the pair buffer as
-# [j1][c2][c3], the pencil pass runs over slabs of fixed c2 (axis 1 and the
-# inverse along axis 3), the accumulate over independent lines along axis 2
+# cubic 72^3 FP32 (the slab path, the default there; FOCK_SLAB=0 turns it
+# off): the plane pass leaves the pair buffer as [j1][c2][c3], the pencil
+# pass runs over slabs of fixed c2 (axis 1 and the inverse along axis 3), the
+# accumulate over independent lines along axis 2
 SLAB_CASES = [
     ((72, 72, 72), (2, 1, 1), 2, "c64", 6),     # 2 pairs per block budget -> blocks of one orbital
     ((72, 72, 72), (1, 1, 1), 3, "c64", 4096),  # one block: a triangular batch only
@@ -211,8 +212,8 @@ def test_slab_pencil_matches_oracle(grid, kmesh, nb, prec, tbuf, device, monkeyp
 
     monkeypatch.setenv("FOCK_SLAB", "1")
     test_pair_symmetric_batches_match_oracle(grid, kmesh, nb, prec, tbuf, device)
-    # the slab path was taken: its axis-3 transform runs over lane pairs, so the
-    # FP32 results differ in the last bits from the one-lane path's
+    # the slab path was taken: its transforms run in another order than the
+    # plane-wise accumulate's, so the FP32 results differ in the last bits
     inst = inputs.small_instance(grid=grid, kmesh=kmesh, nbands=nb, seed=(310, sum(grid) + nb))
     psi = torch.from_numpy(np.ascontiguousarray(inst.psi.astype(np.complex64))).to(device)
     occ = torch.from_numpy(np.ascontiguousarray(inst.occ)).to(device)
