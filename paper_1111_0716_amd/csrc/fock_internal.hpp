@@ -224,6 +224,8 @@ bool reg_supported(fock_precision prec, const int grid[3]);
 // grids where the register-line path can run its pencil pass over slabs of
 // fixed c2 (and the accumulate over independent lines)
 bool reg_slab_supported(fock_precision prec, const int grid[3]);
+// where it is taken without FOCK_SLAB=1 (measured per size)
+bool reg_slab_default(fock_precision prec, const int grid[3]);
 size_t reg_lds_bytes(fock_precision prec, int L);
 void prepare_reg_kernels(fock_precision prec, int lim);
 // energy: the pencil pass also writes the batch's weighted pair energies to

@@ -973,7 +973,7 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
 // Rows and partners as in k_acc_reg.
 // ---------------------------------------------------------------------------
 template <typename T, int L>
-__global__ __launch_bounds__(256, 1) void k_acc_line(
+__global__ __launch_bounds__(256, (RegShape<T, L>::WPE_ACC)) void k_acc_line(
     int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
     const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
     const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
@@ -1203,7 +1203,7 @@ namespace {
 // lengths compiled with the slab pencil and the line accumulate
 template <typename T, int L>
 constexpr bool slab_len() {
-  return sizeof(T) == 4 && L == 72;
+  return sizeof(T) == 4 && (L == 32 || L == 64 || L == 72);
 }
 
 template <typename T, int L, bool EXPLICIT, typename TI = T>
@@ -1708,7 +1708,15 @@ hipError_t reg_dft3_t(const Plan& p, int inst, int count, void* data, long long 
 }  // namespace
 
 bool reg_slab_supported(fock_precision prec, const int grid[3]) {
-  return prec == FOCK_C64 && grid[0] == 72 && grid[1] == 72 && grid[2] == 72;
+  const int n = grid[0];
+  return prec == FOCK_C64 && grid[1] == n && grid[2] == n && (n == 32 || n == 64 || n == 72);
+}
+
+// measured: alpha boron 32^3 370 against 385 ms per step, beta boron 72^3 7.20
+// against 8.04 s; the 64^3 preset 54.9 against 46.6 ms (there the line
+// accumulate holds a whole SIMD's registers, the lane-pair one two waves)
+bool reg_slab_default(fock_precision prec, const int grid[3]) {
+  return reg_slab_supported(prec, grid) && (grid[0] == 32 || grid[0] == 72);
 }
 
 bool reg_supported(fock_precision prec, const int grid[3]) {

@@ -302,9 +302,10 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
   const bool no_reg = noreg && *noreg && *noreg != '0';
   const char* nosym = std::getenv("FOCK_NO_PAIR_SYMMETRY");
   const bool no_sym = tn.no_pair_symmetry != 0 || (nosym && *nosym && *nosym != '0');
-  // FOCK_SLAB=0 keeps cubic grids on the plane-wise accumulate (measurement switch)
+  // FOCK_SLAB=0 keeps every grid on the plane-wise accumulate, FOCK_SLAB=1 puts
+  // every supported cubic grid on the slab path (measurement switch)
   const char* slab_env = std::getenv("FOCK_SLAB");
-  const bool use_slab = !(slab_env && *slab_env == '0');
+  const int slab_force = slab_env && *slab_env ? (*slab_env != '0' ? 1 : 0) : -1;
   const char* rounds_env = std::getenv("FOCK_FUSED_ROUNDS");
   const bool use_rounds = tn.fused_rounds != 0 || (rounds_env && *rounds_env && *rounds_env != '0');
   for (auto& in : p->inst) {
@@ -317,7 +318,8 @@ fock_status build_plan(const fock_desc* descs, int n_inst, fock_precision prec, 
     const bool mixed = prec == FOCK_MIXED || prec == FOCK_MIXED_INV;
     in.fused = !mixed && fused_supported(prec, in.grid) && !no_fused && !sym_three_pass;
     in.reg = !in.fused && reg_supported(prec, in.grid) && !no_reg;
-    in.slab = in.reg && use_slab && reg_slab_supported(prec, in.grid);
+    in.slab = in.reg && (slab_force < 0 ? reg_slab_default(prec, in.grid)
+                                        : slab_force == 1 && reg_slab_supported(prec, in.grid));
     if (mixed && !in.reg)
       return set_error(FOCK_ERR_UNSUPPORTED, "mixed precision needs a grid N1 x L x L with N1 and L in {24, 32, 36, 40, 48, 50, 54, 60, 64, 72}");
   }
