@@ -467,10 +467,14 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
   extern __shared__ unsigned char smem_raw[];
   T* sp = reinterpret_cast<T*>(smem_raw);
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
-  const int j1 = blockIdx.x * Sh::PL + pl;
+  // rows fastest in the grid: the workgroups of one plane block for all rows,
+  // which read the same slices of the partners' orbitals, run together
+  const int xb = static_cast<int>(blockIdx.y);
+  const int row = static_cast<int>(blockIdx.x);
+  const int j1 = xb * Sh::PL + pl;
   const bool valid = j1 < n1;
-  const bool mirror = static_cast<int>(blockIdx.y) >= nO;
-  const int o = mirror ? static_cast<int>(blockIdx.y) - nO : static_cast<int>(blockIdx.y);
+  const bool mirror = row >= nO;
+  const int o = mirror ? row - nO : row;
   const int nsrc = mirror ? nO : nP;
   sp += pl * L * Sh::LP;
   C acc[L];
@@ -498,7 +502,7 @@ __global__ __launch_bounds__((RegShape<T, L>::NTP), (RegShape<T, L>::WPE_ACC)) v
       size_t pair1;
       bool cj1;
       acc_source(mirror, p + 1 < nsrc ? p + 1 : p, o, o0, nP, tri, nbands, parts, &sb1, &pair1, &cj1);
-      const int j10 = static_cast<int>(blockIdx.x) * Sh::PL;
+      const int j10 = xb * Sh::PL;
       const int planes = min(Sh::PL, n1 - j10);
       prefetch_l2<Sh::NTP, Sh::PF_ACC>(tbuf + (pair1 * n1 + j10) * LL, static_cast<unsigned>(planes * LL * sizeof(C)), t,
                                        pfv);
@@ -876,10 +880,14 @@ __global__ __launch_bounds__((SplitShape<T, L>::NTP), (SplitShape<T, L>::WPE_ACC
   constexpr int NB = LH / B;
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / Sh::TPP, rem = t - pl * Sh::TPP, col = rem >> 1, h = rem & 1;
-  const int j1 = blockIdx.x * Sh::PL + pl;
+  // rows fastest in the grid: the workgroups of one plane block for all rows,
+  // which read the same slices of the partners' orbitals, run together
+  const int xb = static_cast<int>(blockIdx.y);
+  const int row = static_cast<int>(blockIdx.x);
+  const int j1 = xb * Sh::PL + pl;
   const bool valid = j1 < n1;
-  const bool mirror = static_cast<int>(blockIdx.y) >= nO;
-  const int o = mirror ? static_cast<int>(blockIdx.y) - nO : static_cast<int>(blockIdx.y);
+  const bool mirror = row >= nO;
+  const int o = mirror ? row - nO : row;
   T* sp = reinterpret_cast<T*>(smem_raw) + pl * L * Sh::LP;
   // element (j1, 2m + h, col) of a grid: the lane's samples along axis 2
   const size_t eo = static_cast<size_t>(j1) * LL + static_cast<size_t>(h) * L + col;
@@ -1344,13 +1352,13 @@ void launch_acc_kernel(const Plan& p, const Batch& b, const Instance& in, const 
   const int rows = b.nO + (b.mirror ? b.nP : 0);
   if constexpr (SPLIT) {
     using Sh = SplitShape<T, L>;
-    hipLaunchKernelGGL((k_acc_split<T, L, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS,
+    hipLaunchKernelGGL((k_acc_split<T, L, TI>), dim3(rows, (n1 + Sh::PL - 1) / Sh::PL), dim3(Sh::NTP), Sh::LDS,
                        p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi),
                        occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
   } else {
     using Sh = RegShape<T, L>;
     constexpr bool PF = sizeof(TI) == sizeof(T) && RegPolicy<T, L>::ACC_PREFETCH;
-    hipLaunchKernelGGL((k_acc_reg<T, L, TI, PF>), dim3((n1 + Sh::PL - 1) / Sh::PL, rows), dim3(Sh::NTP), Sh::LDS,
+    hipLaunchKernelGGL((k_acc_reg<T, L, TI, PF>), dim3(rows, (n1 + Sh::PL - 1) / Sh::PL), dim3(Sh::NTP), Sh::LDS,
                        p.stream, n1, in.nbands, bs, b.o0, b.nO, b.nP, b.tri, parts, tbuf, static_cast<const C*>(psi),
                        occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale, hscale, backward ? 1 : 0);
   }
