@@ -254,15 +254,16 @@ __device__ __forceinline__ void lds_round_trip(C* x, T* sp, int col) {
 template <typename T, int L, bool EXPLICIT, typename TI = T, bool SLAB = false>
 __global__ __launch_bounds__((RegShape<T, L>::NTP), (sizeof(TI) == sizeof(T) ? RegShape<T, L>::WPE_PLANE : 1)) void k_plane_reg(
     int n1, int nbands, long long bs, const typename cx<TI>::t* __restrict__ psi, int o0, int nP, int tri,
-    const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf) {
+    const int2* __restrict__ parts, const PairRef* __restrict__ pairs, typename cx<T>::t* __restrict__ tbuf, int pf) {
   using C = typename cx<T>::t;
   using Sh = RegShape<T, L>;
   constexpr int LL = L * L;
   extern __shared__ unsigned char smem_raw[];
   const int t = threadIdx.x, pl = t / L, col = t - (t / L) * L;
-  const int j1 = blockIdx.x * Sh::PL + pl;
+  // pf: pairs fastest in the grid (blockIdx.x the pair slot)
+  const int j1 = static_cast<int>(pf ? blockIdx.y : blockIdx.x) * Sh::PL + pl;
   const bool valid = j1 < n1;
-  const int pi = blockIdx.y;
+  const int pi = static_cast<int>(pf ? blockIdx.x : blockIdx.y);
   int okn, pkm;
   if (EXPLICIT) {
     const PairRef pr = pairs[pi];
@@ -1230,7 +1231,8 @@ void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void*
   if constexpr (sizeof(TI) != sizeof(T)) {  // FOCK_MIXED: one-lane FP32 lines from FP64 orbitals
     using Sh = RegShape<T, L>;
     hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, TI>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
-                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const CI*>(psi), o0, nP, tri, parts, pairs, tbuf);
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const CI*>(psi), o0, nP, tri, parts, pairs, tbuf,
+                       0);
   } else if constexpr (Po::SPLIT_PLANE) {
     using Sh = SplitShape<T, L>;
     hipLaunchKernelGGL((k_plane_split<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
@@ -1241,12 +1243,17 @@ void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void*
       if (in.slab) {  // pair buffer [j1][c2][c3] for the slab pencil
         hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, T, true>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs),
                            dim3(Sh::NTP), Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP,
-                           tri, parts, pairs, tbuf);
+                           tri, parts, pairs, tbuf, 0);
         return;
       }
     }
-    hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs), dim3(Sh::NTP),
-                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, tri, parts, pairs, tbuf);
+    // FP64: pairs fastest in the grid (alpha boron FP64 plane pass 180 against
+    // 207 ms per step; FP32 on the slab path loses with it)
+    constexpr int pf = sizeof(T) == 8 ? 1 : 0;
+    const int nxb = (n1 + Sh::PL - 1) / Sh::PL;
+    hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT>), pf ? dim3(b.npairs, nxb) : dim3(nxb, b.npairs), dim3(Sh::NTP),
+                       Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP, tri, parts, pairs, tbuf,
+                       pf);
   }
 }
 
