@@ -1058,6 +1058,85 @@ __global__ __launch_bounds__(256, (RegShape<T, L>::WPE_ACC)) void k_acc_line(
   }
 }
 
+// the line accumulate over lane pairs, where one lane per line would need a
+// whole SIMD's registers: lane h of a pair loads c2 = h L/2 + k of the line
+// (j1, j3) and holds j2 = 2m + h after the transform (see split_fft.hpp)
+template <typename T, int L>
+__global__ __launch_bounds__(256, (SplitShape<T, L>::WPE_ACC)) void k_acc_line_split(
+    int nbands, long long bs, int o0, int nO, int nP, int tri, const int2* __restrict__ parts,
+    const typename cx<T>::t* __restrict__ tbuf, const typename cx<T>::t* __restrict__ psi,
+    const double* __restrict__ occ, const double* __restrict__ kw, typename cx<T>::t* __restrict__ out, int first,
+    int first_mirror, const double* __restrict__ gscale, double hscale, int backward) {
+  using C = typename cx<T>::t;
+  using Sh = SplitShape<T, L>;
+  constexpr int LL = L * L, LH = Sh::LH;
+  constexpr int B = batch_of(LH, Sh::WPE_ACC == 1 ? 16 : kRegB);
+  constexpr int NB = LH / B;
+  const int h = threadIdx.x & 1;
+  // rows fastest in the grid (see k_acc_line)
+  const int l = static_cast<int>(blockIdx.y) * 128 + static_cast<int>(threadIdx.x >> 1);  // line (j1, j3)
+  if (l >= LL) return;  // both lanes of a pair together; no barrier in this kernel
+  const int row = static_cast<int>(blockIdx.x);
+  const bool mirror = row >= nO;
+  const int o = mirror ? row - nO : row;
+  const int nsrc = mirror ? nO : nP;
+  const int j1 = l / L, j3 = l - (l / L) * L;
+  const size_t eoff = static_cast<size_t>(j1) * LL + j3;  // element (j1, 0, j3); axis 2 has stride L
+  C acc[LH];
+#pragma unroll
+  for (int m = 0; m < LH; ++m) acc[m] = C{T(0), T(0)};
+  for (int p = 0; p < nsrc; ++p) {
+    int sb;
+    size_t pair;
+    bool cj;
+    acc_source(mirror, p, o, o0, nP, tri, nbands, parts, &sb, &pair, &cj);
+    const C* src = tbuf + pair * LL * L + eoff + static_cast<size_t>(h) * LH * L;
+    C y[LH];
+#pragma unroll
+    for (int k = 0; k < LH; ++k) y[k] = src[k * L];  // c2 = h L/2 + k
+    split_fft_inv<C, L>(y, h);                       // y[m] at j2 = 2m + h
+    if (cj) {
+#pragma unroll
+      for (int m = 0; m < LH; ++m) y[m].y = -y[m].y;
+    }
+    const T coef = static_cast<T>(-kw[sb / nbands] * occ[sb]);
+    const C* um = psi + static_cast<size_t>(sb) * bs + eoff + static_cast<size_t>(h) * L;
+    C mb[2][B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) mb[0][j] = um[j * 2 * L];
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      if (n + 1 < NB) {
+#pragma unroll
+        for (int j = 0; j < B; ++j) mb[(n + 1) & 1][j] = um[((n + 1) * B + j) * 2 * L];
+      }
+      reg_fence();
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const C w = cmul(mb[n & 1][j], y[n * B + j]);
+        acc[n * B + j].x += coef * w.x;
+        acc[n * B + j].y += coef * w.y;
+      }
+    }
+  }
+  const int okn = mirror ? parts[o].x * nbands + parts[o].y : o0 + o;
+  double f = hscale;
+  if (gscale) f *= gscale[0];
+  if (backward) f *= kw[okn / nbands] * occ[okn];
+  const T ft = static_cast<T>(f);
+  C* dst = out + static_cast<size_t>(okn) * bs + eoff + static_cast<size_t>(h) * L;
+  if (!(mirror ? first_mirror : first)) {
+    C old[LH];  // loaded before the first store (see k_acc_reg)
+#pragma unroll
+    for (int m = 0; m < LH; ++m) old[m] = dst[m * 2 * L];
+#pragma unroll
+    for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cadd(old[m], cscale(acc[m], ft));
+  } else {
+#pragma unroll
+    for (int m = 0; m < LH; ++m) dst[m * 2 * L] = cscale(acc[m], ft);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // mixed precision (FOCK_MIXED): pencil pass from the FP32 pair buffer to the
 // FP64 one: forward axis 1 in FP32, kernel multiply and inverse in FP64
@@ -1216,7 +1295,14 @@ namespace {
 // lengths compiled with the slab pencil and the line accumulate
 template <typename T, int L>
 constexpr bool slab_len() {
-  return sizeof(T) == 4 && (L == 32 || L == 64 || L == 72);
+  return sizeof(T) == 4 ? (L == 32 || L == 64 || L == 72) : L == 32;
+}
+
+// the line accumulate over lane pairs where one lane per line would take a
+// whole SIMD's registers (line and accumulator over 160 registers)
+template <typename T, int L>
+constexpr bool line_split() {
+  return 2 * RegShape<T, L>::LINE_REGS > 160 && L != 72;
 }
 
 template <typename T, int L, bool EXPLICIT, typename TI = T>
@@ -1241,9 +1327,11 @@ void launch_plane(const Plan& p, const Batch& b, const Instance& in, const void*
     using Sh = RegShape<T, L>;
     if constexpr (slab_len<T, L>()) {
       if (in.slab) {  // pair buffer [j1][c2][c3] for the slab pencil
-        hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, T, true>), dim3((n1 + Sh::PL - 1) / Sh::PL, b.npairs),
+        constexpr int pf = sizeof(T) == 8 ? 1 : 0;  // as below
+        const int nxb = (n1 + Sh::PL - 1) / Sh::PL;
+        hipLaunchKernelGGL((k_plane_reg<T, L, EXPLICIT, T, true>), pf ? dim3(b.npairs, nxb) : dim3(nxb, b.npairs),
                            dim3(Sh::NTP), Sh::LDS, p.stream, n1, in.nbands, bs, static_cast<const C*>(psi), o0, nP,
-                           tri, parts, pairs, tbuf, 0);
+                           tri, parts, pairs, tbuf, pf);
         return;
       }
     }
@@ -1286,10 +1374,16 @@ bool launch_acc_line(const Plan& p, const Batch& b, const Instance& in, const in
   if constexpr (slab_len<T, L>()) {
     using C = typename cx<T>::t;
     const int rows = b.nO + (b.mirror ? b.nP : 0);
-    hipLaunchKernelGGL((k_acc_line<T, L>), dim3(rows, (L * L + 255) / 256), dim3(256), 0, p.stream, in.nbands,
-                       static_cast<long long>(in.band_stride), b.o0, b.nO, b.nP, b.tri, parts, tbuf,
-                       static_cast<const C*>(psi), occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale,
-                       hscale, backward ? 1 : 0);
+    if constexpr (line_split<T, L>())
+      hipLaunchKernelGGL((k_acc_line_split<T, L>), dim3(rows, (L * L + 127) / 128), dim3(256), 0, p.stream,
+                         in.nbands, static_cast<long long>(in.band_stride), b.o0, b.nO, b.nP, b.tri, parts, tbuf,
+                         static_cast<const C*>(psi), occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale,
+                         hscale, backward ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_acc_line<T, L>), dim3(rows, (L * L + 255) / 256), dim3(256), 0, p.stream, in.nbands,
+                         static_cast<long long>(in.band_stride), b.o0, b.nO, b.nP, b.tri, parts, tbuf,
+                         static_cast<const C*>(psi), occ, kw, static_cast<C*>(out), b.first, b.first_mirror, gscale,
+                         hscale, backward ? 1 : 0);
     return true;
   } else {
     return false;
@@ -1399,6 +1493,14 @@ void reg_lds_attr(int lim) {
   fs[3] = fs[2];
   for (const void* f : fs)
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+  if constexpr (slab_len<T, L>()) {
+    const void* gs[4] = {reinterpret_cast<const void*>(&k_plane_reg<T, L, false, T, true>),
+                         reinterpret_cast<const void*>(&k_plane_reg<T, L, true, T, true>),
+                         reinterpret_cast<const void*>(&k_pencil_slab<T, L, false>),
+                         reinterpret_cast<const void*>(&k_pencil_slab<T, L, true>)};
+    for (const void* f : gs)
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim) != hipSuccess) (void)hipGetLastError();
+  }
 }
 
 // FOCK_MIXED: FP32 plane pass (FP64 orbitals rounded on load), mixed pencil
@@ -1728,14 +1830,17 @@ hipError_t reg_dft3_t(const Plan& p, int inst, int count, void* data, long long 
 
 bool reg_slab_supported(fock_precision prec, const int grid[3]) {
   const int n = grid[0];
-  return prec == FOCK_C64 && grid[1] == n && grid[2] == n && (n == 32 || n == 64 || n == 72);
+  if (grid[1] != n || grid[2] != n) return false;
+  if (prec == FOCK_C64) return n == 32 || n == 64 || n == 72;
+  return prec == FOCK_C128 && n == 32;
 }
 
-// measured: alpha boron 32^3 370 against 385 ms per step, beta boron 72^3 7.20
-// against 8.04 s; the 64^3 preset 54.9 against 46.6 ms (there the line
-// accumulate holds a whole SIMD's registers, the lane-pair one two waves)
+// measured per step: alpha boron 32^3 FP32 370 against 385 ms, FP64 758
+// against 886 ms; beta boron 72^3 7.20 against 8.04 s; the 64^3 preset FP32
+// 42.8 against 46.5 ms (with the lane-pair line accumulate; one lane per
+// line, a whole SIMD's registers, took 54.9 ms)
 bool reg_slab_default(fock_precision prec, const int grid[3]) {
-  return reg_slab_supported(prec, grid) && (grid[0] == 32 || grid[0] == 72);
+  return reg_slab_supported(prec, grid);
 }
 
 bool reg_supported(fock_precision prec, const int grid[3]) {
