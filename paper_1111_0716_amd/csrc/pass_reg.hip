@@ -1295,7 +1295,7 @@ namespace {
 // lengths compiled with the slab pencil and the line accumulate
 template <typename T, int L>
 constexpr bool slab_len() {
-  return sizeof(T) == 4 ? (L == 32 || L == 64 || L == 72) : L == 32;
+  return sizeof(T) == 4 ? true : L <= 32;  // FP64: the one-lane plane lengths
 }
 
 // the line accumulate over lane pairs where one lane per line would take a
@@ -1830,17 +1830,25 @@ hipError_t reg_dft3_t(const Plan& p, int inst, int count, void* data, long long 
 
 bool reg_slab_supported(fock_precision prec, const int grid[3]) {
   const int n = grid[0];
-  if (grid[1] != n || grid[2] != n) return false;
-  if (prec == FOCK_C64) return n == 32 || n == 64 || n == 72;
-  return prec == FOCK_C128 && n == 32;
+  if (grid[1] != n || grid[2] != n || !reg_supported(prec, grid)) return false;
+  if (prec == FOCK_C64) return true;
+  return prec == FOCK_C128 && n <= 32;
 }
 
 // measured per step: alpha boron 32^3 FP32 370 against 385 ms, FP64 758
 // against 886 ms; beta boron 72^3 7.20 against 8.04 s; the 64^3 preset FP32
 // 42.8 against 46.5 ms (with the lane-pair line accumulate; one lane per
-// line, a whole SIMD's registers, took 54.9 ms)
+// line, a whole SIMD's registers, took 54.9 ms).  Cubic cells with 2x2x2 k
+// (apply + energy + gradient): FP32 36^3 69.9 against 72.5 ms, 40^3 92.9
+// against 100.9, 48^3 71.1 against 73.1, 50^3 89.9 against 100.7; FP64 24^3
+// 34.7 against 43.9.  Kept plane-wise: FP32 54^3 (119.0 against 116.7 ms)
+// and 60^3 (93.7 against 87.7); FP32 24^3 stays on the whole-pair kernel
+// (17.1 ms against 19.8 on the slab path).
 bool reg_slab_default(fock_precision prec, const int grid[3]) {
-  return reg_slab_supported(prec, grid);
+  const int n = grid[0];
+  if (!reg_slab_supported(prec, grid)) return false;
+  if (prec == FOCK_C128) return true;  // 24^3 and 32^3
+  return n == 32 || n == 36 || n == 40 || n == 48 || n == 50 || n == 64 || n == 72;
 }
 
 bool reg_supported(fock_precision prec, const int grid[3]) {
