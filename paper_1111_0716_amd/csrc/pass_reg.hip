@@ -1298,11 +1298,15 @@ constexpr bool slab_len() {
   return sizeof(T) == 4 ? true : L <= 32;  // FP64: the one-lane plane lengths
 }
 
-// the line accumulate over lane pairs where one lane per line would take a
-// whole SIMD's registers (line and accumulator over 160 registers)
+// the line accumulate over lane pairs: FP64 where line and accumulator take
+// over 160 registers, FP32 at 60 and 64 points.  Measured on the slab path
+// (cubic cells, 2x2x2 k, apply + energy + gradient per step), one lane per
+// line against lane pairs: 48^3 70.7 against 71.1 ms, 50^3 84.5 against
+// 89.9, 54^3 111.9 against 119.0, 60^3 105.0 against 93.7, 64^3 54.9 against
+// 42.8; at 72^3 one lane wins (beta boron)
 template <typename T, int L>
 constexpr bool line_split() {
-  return 2 * RegShape<T, L>::LINE_REGS > 160 && L != 72;
+  return sizeof(T) == 4 ? (L == 60 || L == 64) : 2 * RegShape<T, L>::LINE_REGS > 160;
 }
 
 template <typename T, int L, bool EXPLICIT, typename TI = T>
@@ -1840,15 +1844,15 @@ bool reg_slab_supported(fock_precision prec, const int grid[3]) {
 // 42.8 against 46.5 ms (with the lane-pair line accumulate; one lane per
 // line, a whole SIMD's registers, took 54.9 ms).  Cubic cells with 2x2x2 k
 // (apply + energy + gradient): FP32 36^3 69.9 against 72.5 ms, 40^3 92.9
-// against 100.9, 48^3 71.1 against 73.1, 50^3 89.9 against 100.7; FP64 24^3
-// 34.7 against 43.9.  Kept plane-wise: FP32 54^3 (119.0 against 116.7 ms)
-// and 60^3 (93.7 against 87.7); FP32 24^3 stays on the whole-pair kernel
-// (17.1 ms against 19.8 on the slab path).
+// against 100.9, 48^3 70.7 against 72.9, 50^3 84.5 against 100.5, 54^3 111.9
+// against 116.5; FP64 24^3 34.7 against 43.9.  Kept plane-wise: FP32 60^3
+// (93.7 against 87.6 ms); FP32 24^3 stays on the whole-pair kernel (17.1 ms
+// against 19.8 on the slab path).
 bool reg_slab_default(fock_precision prec, const int grid[3]) {
   const int n = grid[0];
   if (!reg_slab_supported(prec, grid)) return false;
   if (prec == FOCK_C128) return true;  // 24^3 and 32^3
-  return n == 32 || n == 36 || n == 40 || n == 48 || n == 50 || n == 64 || n == 72;
+  return n != 24 && n != 60;
 }
 
 bool reg_supported(fock_precision prec, const int grid[3]) {

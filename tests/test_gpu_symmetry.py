@@ -206,10 +206,10 @@ SLAB_CASES = [
     ((24, 24, 24), (2, 1, 1), 3, "c128", 4096),  # FP64 line accumulate over lane pairs
     ((36, 36, 36), (1, 1, 1), 3, "c64", 4096),
     ((40, 40, 40), (2, 1, 1), 2, "c64", 6),      # blocks of one orbital
-    ((48, 48, 48), (1, 1, 1), 3, "c64", 4096),   # FP32 line accumulate over lane pairs
+    ((48, 48, 48), (1, 1, 1), 3, "c64", 4096),
     ((50, 50, 50), (1, 1, 1), 2, "c64", 4096),
     ((54, 54, 54), (1, 1, 1), 2, "c64", 4096),
-    ((60, 60, 60), (1, 1, 1), 2, "c64", 4096),
+    ((60, 60, 60), (1, 1, 1), 2, "c64", 4096),   # FP32 line accumulate over lane pairs
 ]
 
 
